@@ -1,0 +1,178 @@
+/*
+ * pcv.h -- C ABI of the MI355X parallel cross-validation library.
+ *
+ * Computes the parallel CV loss of Gerber & Nychka, "Parallel
+ * cross-validation: a scalable fitting method for Gaussian process models"
+ * (arXiv:1912.13132) on one AMD Instinct MI355X (gfx950), and kriging
+ * predictions from the resulting per-subset factors.
+ *
+ *   model            Sec. 2.1, eq. (1):  y ~ N(0, sigma^2 Sigma(theta) + tau I)
+ *   kriging          Sec. 2.1, eq. (3):  yhat = Sigma_p^T (Sigma + lambda I)^{-1} y,
+ *                                        lambda = tau / sigma^2
+ *   hold-out loss    Sec. 2.2, eq. (4):  SSPE = sum_v (yhat_v - y_v)^2
+ *   parallel CV      Sec. 2.3, eq. (7) and Algorithm 1:
+ *                                        CV~ = sum_i CV(y~^i_T, y^i_V, zeta)
+ *   covariance       Sec. 3:             c(d) = exp(-d / theta)
+ *
+ * Conventions shared by every call
+ *   - Every call returns a pcv_status; PCV_OK (0) is success.  On failure
+ *     pcv_last_error() returns a thread-local message naming the offending
+ *     argument / subset.
+ *   - All validation happens before any device work: a call that returns
+ *     PCV_ERR_INVALID has had no side effects.
+ *   - Host arrays are owned by the caller and only read (inputs) or written
+ *     (outputs) during the call.  pcv_problem_create copies its inputs to
+ *     device memory; the problem owns those copies.
+ *   - Locations are row-major (x, y) pairs in float64.  Index arrays are
+ *     0-based.  A subset's training and validation points are given as CSR:
+ *     subset i trains on train_idx[train_ptr[i] .. train_ptr[i+1]) and
+ *     validates on val_idx[val_ptr[i] .. val_ptr[i+1]).
+ *   - One caller thread per pcv_problem.  Different problems may be used
+ *     from different threads.
+ *   - The library runs on the HIP device that is current when the problem
+ *     is created and uses that device for the problem's lifetime.
+ */
+#ifndef PCV_H
+#define PCV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PCV_OK = 0,
+  PCV_ERR_INVALID = 1, /* bad argument; nothing was done                      */
+  PCV_ERR_OOM = 2,     /* device or pinned memory exhausted / over the cap     */
+  PCV_ERR_NOT_PD = 3,  /* a subset matrix is not positive definite in FP64     */
+  PCV_ERR_DEVICE = 4,  /* a HIP runtime call failed                            */
+  PCV_ERR_STATE = 5,   /* call out of order (e.g. predict before factor)       */
+  PCV_ERR_BUSY = 6     /* a wait timed out / the server is shutting down       */
+} pcv_status;
+
+/* Covariance family.  PCV_COV_EXP is the paper's exponential covariance
+ * (Sec. 3).  PCV_COV_MATERN32 is the Matern nu = 3/2 member of the same
+ * parametrisation, c(d) = (1 + d/theta) exp(-d/theta). */
+typedef enum { PCV_COV_EXP = 0, PCV_COV_MATERN32 = 1 } pcv_cov;
+
+/* Arithmetic of a theta-evaluation.
+ * PCV_PREC_FP64:  covariance, Cholesky, solves, prediction and loss in FP64
+ *                 (the factorisation's tile updates on FP64 MFMA).
+ * PCV_PREC_MIXED: covariance tiles and the bulk of the Cholesky in FP32
+ *                 (FP32 MFMA, FP32 accumulation); diagonal blocks factored in
+ *                 FP64; solves accumulate in FP64; iterative refinement with
+ *                 an FP64 residual regenerated from FP64 coordinates; FP64
+ *                 prediction and loss. */
+typedef enum { PCV_PREC_FP64 = 0, PCV_PREC_MIXED = 1 } pcv_prec;
+
+/* zeta of Sec. 2.1: range theta > 0 and noise-to-signal ratio
+ * lambda = tau / sigma^2 >= 0.  sigma2 > 0 only scales kriging variances
+ * (it cancels from eq. (3) and eq. (4)). */
+typedef struct {
+  int32_t cov;   /* pcv_cov */
+  double range;  /* theta  */
+  double lambda; /* lambda */
+  double sigma2; /* sigma^2 */
+} pcv_theta;
+
+typedef struct {
+  int32_t prec;           /* pcv_prec; default PCV_PREC_MIXED                        */
+  int32_t max_refine;     /* mixed: refinement sweeps (default 1, max 8)             */
+  double refine_tol;      /* mixed: stop when ||r||_2 <= tol * ||y_T||_2 (1e-12)     */
+  void* hip_stream;       /* hipStream_t to run on; NULL = library-owned stream      */
+  size_t mem_cap_bytes;   /* device workspace cap, 0 = no cap                         */
+  int32_t profile;        /* nonzero: time each kernel phase with HIP events          */
+  int32_t reserved[7];
+} pcv_options;
+
+/* Per-evaluation report.  Arrays are optional, caller-owned, length S. */
+typedef struct {
+  double sspe;               /* = *loss                                             */
+  int64_t n_val;             /* validation points over non-skipped subsets          */
+  double mse;                /* sspe / n_val                                        */
+  int32_t n_subsets_used;    /* subsets with >= 1 validation point                  */
+  int32_t n_fallback_fp64;   /* mixed: subsets re-run in FP64                       */
+  int32_t max_refine_iters;  /* mixed: largest number of sweeps any subset used     */
+  int32_t pad0;
+  double max_rel_residual;   /* mixed: max_i ||r_i|| / ||y_i|| after refinement     */
+  double seconds;            /* wall time of the call                               */
+  /* phase times in ms (HIP events on the evaluation stream), when profiling */
+  double ms_factor, ms_solve, ms_refine, ms_predict, ms_reduce;
+  double* per_subset_sspe;   /* optional out [S]: z_i (0 for skipped subsets)       */
+  double* per_subset_logdet; /* optional out [S]: log det(Sigma_i + lambda I)       */
+  int32_t* per_subset_iters; /* optional out [S]: refinement sweeps used            */
+} pcv_eval_report;
+
+typedef struct pcv_problem pcv_problem;
+
+void pcv_default_options(pcv_options* opt);
+
+/* Make a problem resident on the current device (Algorithm 1, steps 2-5:
+ * the data are divided and read once, then evaluated for many zeta).
+ *   n          number of locations (>= 1)
+ *   locs       host float64 [n][2]
+ *   y          host float64 [n]
+ *   S          number of subsets (>= 1)
+ *   train_ptr  host int64 [S+1], nondecreasing, train_ptr[0] = 0
+ *   train_idx  host int32 [train_ptr[S]], each in [0, n)
+ *   val_ptr    host int64 [S+1], nondecreasing, val_ptr[0] = 0
+ *   val_idx    host int32 [val_ptr[S]], each in [0, n)
+ *   core_rect  host float64 [S][4] (xlo, ylo, xhi, yhi) of each core, used to
+ *              route prediction queries; may be NULL (then pcv_predict routes
+ *              every query to the subset whose training centroid is nearest)
+ *   opt        may be NULL (defaults)
+ * Subsets without validation points are kept but never evaluated (they
+ * contribute 0, as in Sec. 4.3.1).  A subset larger than the library's
+ * maximum (PCV_MAX_SUBSET training points) is rejected with PCV_ERR_INVALID.
+ * Errors: PCV_ERR_INVALID (sizes, NaN/Inf, index range, ptr order),
+ * PCV_ERR_OOM, PCV_ERR_DEVICE. */
+#define PCV_MAX_SUBSET 16384
+pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs,
+                              const double* y, int32_t S, const int64_t* train_ptr,
+                              const int32_t* train_idx, const int64_t* val_ptr,
+                              const int32_t* val_idx, const double* core_rect,
+                              const pcv_options* opt);
+
+/* One theta-evaluation: *loss = CV~ of eq. (7) (the SSPE summed over all
+ * subsets with validation data).  Synchronous: returns after the loss is
+ * on the host.  report may be NULL.
+ * Errors: PCV_ERR_INVALID (theta), PCV_ERR_NOT_PD (an FP64 factorisation
+ * broke down; pcv_last_error names the subset), PCV_ERR_DEVICE. */
+pcv_status pcv_eval(pcv_problem* p, const pcv_theta* theta, double* loss,
+                    pcv_eval_report* report);
+
+/* n_theta evaluations; losses[k] for thetas[k].  Equivalent to n_theta calls
+ * of pcv_eval. */
+pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas,
+                          double* losses);
+
+/* Factor every subset at theta in FP64 and keep L_i and
+ * alpha_i = (Sigma_i + lambda I)^{-1} y_i resident for pcv_predict. */
+pcv_status pcv_factor(pcv_problem* p, const pcv_theta* theta);
+
+/* Kriging at q query locations (host float64 [q][2]) from the factors of
+ * the last pcv_factor: each query is routed to its core (half-open
+ * rectangles, edges on the domain maximum closed, nearest core if outside
+ * all), mean = k^T alpha (eq. (3)) and
+ * var = sigma^2 (1 - k^T (Sigma + lambda I)^{-1} k) (+ sigma^2 lambda when
+ * obs_noise != 0).  var may be NULL.  owner (may be NULL) receives each
+ * query's subset.  Errors: PCV_ERR_STATE before pcv_factor. */
+pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* mean,
+                       double* var, int32_t obs_noise, int32_t* owner);
+
+pcv_status pcv_problem_destroy(pcv_problem* p);
+
+/* Sizes of the problem: subsets, total training memberships, largest
+ * subset, device bytes held. */
+pcv_status pcv_problem_info(const pcv_problem* p, int32_t* S, int64_t* nnz_train,
+                            int32_t* max_train, size_t* device_bytes);
+
+const char* pcv_status_string(pcv_status s);
+const char* pcv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCV_H */
