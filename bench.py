@@ -1,0 +1,181 @@
+"""Seconds per theta-evaluation of the parallel CV loss on one MI355X.
+
+Workload: 5,000,000 points on a jittered 2,170 x 2,712 lattice over
+[0,2000] x [0,2500] with 15% of the nodes removed in random rectangular gaps,
+an exponential-covariance field (range 50, nugget 0.1), the recursive
+division of Sec. 2.4 into 2,400 cores with 20% overlap (shells) and 10% of
+every core held out.  One step = one full theta-evaluation (covariance,
+Cholesky, solves + refinement, kriging of the validation points, loss
+reduction), inputs resident in HBM.
+
+Prints one JSON line.  Besides the timed mixed-precision path it reports the
+plain FP64 GPU path, the relative difference between the two losses, the
+factorisation kernel's fraction of the FP32 MFMA peak (HIP events on the
+library's stream), and the FP64 oracle timed on the host's cores on a
+bounded sample of subsets, extrapolated by n^3 share.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "s per θ-eval @5M pts, CV loss ≤1e-6 rel vs FP64; kriging p99 latency"
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
+
+
+def _oracle_subset(args):
+    """CPU-baseline worker: one subset through the FP64 oracle, one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    locT, yT, locV, yV, kind, rng_, lam = args
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        r = oracle.subset_cv(locT, yT, locV, yV, kind, rng_, lam)
+        return time.perf_counter() - t0, r["sspe"]
+
+
+def cpu_baseline(w, th, gpu_per_subset, sample=48, seed=7):
+    import multiprocessing as mp
+    pt = w.part
+    n = np.diff(pt.train_ptr)
+    m = np.diff(pt.val_ptr)
+    act = np.nonzero(m > 0)[0]
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 4, seed]))
+    pick = np.sort(r.choice(act, size=min(sample, act.size), replace=False))
+    jobs = []
+    for i in pick:
+        T = pt.train_idx[pt.train_ptr[i]:pt.train_ptr[i + 1]]
+        V = pt.val_idx[pt.val_ptr[i]:pt.val_ptr[i + 1]]
+        jobs.append((w.locs[T], w.y[T], w.locs[V], w.y[V], w.cov, th[0], th[1]))
+    cores = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_subset, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    cpu_s = np.array([x[0] for x in res])
+    z = np.array([x[1] for x in res])
+    n3 = n.astype(np.float64) ** 3
+    share = n3[act].sum() / n3[pick].sum()
+    est_single = cpu_s.sum() * share
+    rel = np.abs(gpu_per_subset[pick] - z) / np.maximum(z, 1e-300)
+    return dict(value=est_single / cores, unit="s", cores=cores, kind="oracle",
+                sample=f"{len(pick)} of {act.size} subsets (seeded), {cpu_s.sum():.1f} CPU-s, "
+                       f"extrapolated by n^3 share to all subsets on {cores} cores, one BLAS thread each",
+                single_core_s=est_single, sample_wall_s=wall), float(rel.max())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--max-refine", type=int, default=1)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 5M workload (testing)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(subsets would shard across GPUs with one broadcast and one scalar reduce)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_13132_amd import pcv
+    from paper_1912_13132_amd import workloads as W
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream(0)
+
+    t0 = time.perf_counter()
+    if a.scale >= 1.0:
+        w = W.large()
+    else:
+        s = a.scale
+        w = W.large(n=int(5_000_000 * s), nx=int(2170 * math.sqrt(s)) + 1,
+                    ny=int(2712 * math.sqrt(s)) + 1, W=2000 * math.sqrt(s), H=2500 * math.sqrt(s),
+                    n_cores=max(2, int(2400 * s)))
+    pt = w.part
+    nT = np.diff(pt.train_ptr)
+    mV = np.diff(pt.val_ptr)
+    act = mV > 0
+    log(f"workload generated in {time.perf_counter() - t0:.1f}s: N={len(w.y)} S={pt.n_subsets} "
+        f"train {nT.min()}..{nT.max()} val {mV.min()}..{mV.max()}")
+    th_true = w.theta_true
+    th = pcv.theta(th_true[0], th_true[1], cov=w.cov)
+    flops_potrf = float(np.sum(nT[act].astype(np.float64) ** 3 / 3.0 + nT[act] ** 2 / 2.0 + nT[act] / 6.0))
+
+    def run(prec, steps, warmup):
+        t1 = time.perf_counter()
+        P = pcv.Problem.from_workload(w, prec=prec, max_refine=a.max_refine, stream=stream, profile=True)
+        log(f"[{prec}] problem resident in {time.perf_counter() - t1:.1f}s: {P.info()}")
+        for k in range(warmup):
+            loss, rep = P.eval(th, report=True)
+            log(f"[{prec}] warmup {k}: loss {loss:.12g} {rep['seconds']:.3f}s factor {rep['ms_factor']:.1f}ms")
+        torch.cuda.synchronize()
+        times, facs, reps = [], [], []
+        tt = time.perf_counter()
+        for k in range(steps):
+            loss, rep = P.eval(th, report=True)
+            reps.append(rep)
+            facs.append(rep["ms_factor"])
+            log(f"[{prec}] step {k}: loss {loss:.12g} {rep['seconds']:.3f}s factor {rep['ms_factor']:.1f}ms "
+                f"solve {rep['ms_solve']:.1f} refine {rep['ms_refine']:.1f} predict {rep['ms_predict']:.1f}")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - tt
+        P.close()
+        return loss, reps[-1], total / steps, float(np.mean(facs))
+
+    loss, rep, s_per, ms_fac = run(a.prec, a.steps, a.warmup)
+    out = {
+        "metric": METRIC, "value": s_per, "unit": "s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * s_per, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if a.prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "large fit: 5M jittered-lattice points with 15% in gaps, exponential "
+                               "covariance range 50 nugget 0.1, 2400 recursive cores, 20% overlap",
+                   "n_points": int(len(w.y)), "subsets": int(pt.n_subsets),
+                   "train_min": int(nT.min()), "train_max": int(nT.max()),
+                   "n_val": int(rep["n_val"]), "precision": a.prec, "max_refine": a.max_refine},
+    }
+    peak = PEAK_FP32_MFMA if a.prec == "mixed" else PEAK_FP64_MFMA
+    ach = flops_potrf / (ms_fac * 1e-3) / 1e12
+    out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                       "frac": ach / peak, "traffic": None,
+                       "kernel": "k_potrf<float>" if a.prec == "mixed" else "k_potrf<double>",
+                       "kernel_ms": ms_fac, "flops_per_launch": flops_potrf}
+    out["loss"] = loss
+    out["phase_ms"] = {k: rep[k] for k in ("ms_factor", "ms_solve", "ms_refine", "ms_predict", "ms_reduce")}
+    out["max_rel_residual"] = rep["max_rel_residual"]
+    out["n_fallback_fp64"] = rep["n_fallback_fp64"]
+    if a.prec == "mixed" and not a.no_fp64:
+        loss64, rep64, s64, ms64 = run("fp64", max(2, a.steps // 2), 1)
+        out["fp64_path"] = {"s_per_eval": s64, "loss": loss64, "factor_ms": ms64,
+                            "factor_frac_fp64_peak": flops_potrf / (ms64 * 1e-3) / 1e12 / PEAK_FP64_MFMA}
+        out["rel_err_vs_fp64"] = abs(loss - loss64) / abs(loss64)
+        out["speedup_vs_fp64_path"] = s64 / s_per
+    if not a.no_cpu:
+        cb, rel = cpu_baseline(w, th_true, rep["per_subset_sspe"])
+        out["cpu_baseline"] = cb
+        out["oracle_sample_max_rel_err"] = rel
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

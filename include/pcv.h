@@ -84,7 +84,10 @@ typedef struct {
   void* hip_stream;       /* hipStream_t to run on; NULL = library-owned stream      */
   size_t mem_cap_bytes;   /* device workspace cap, 0 = no cap                         */
   int32_t profile;        /* nonzero: time each kernel phase with HIP events          */
-  int32_t reserved[7];
+  int32_t debug_flags;    /* testing hook, 0 in production.  Bit 0: in mixed mode
+                             treat every FP32 factorisation as broken down, so the
+                             FP64 fallback path runs for every subset              */
+  int32_t reserved[6];
 } pcv_options;
 
 /* Per-evaluation report.  Arrays are optional, caller-owned, length S. */

@@ -1,0 +1,192 @@
+// C ABI of the parallel CV library: argument validation, device residency of
+// a divided problem (Algorithm 1, steps 2-5 of arXiv:1912.13132: divide and
+// read once), and the sequence of kernels of one theta-evaluation
+// (Algorithm 1, steps 6-9).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/pcv.h"
+#include "pcv_device.h"
+#include "pcv_host.h"
+
+using pcv::SubsetDesc;
+using pcv::TB;
+
+namespace pcv {
+thread_local std::string g_err;
+pcv_status fail(pcv_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+}  // namespace pcv
+
+using pcv::fail;
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,                \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+namespace {
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+pcv_status check_theta(const pcv_theta* t) {
+  if (!t) return fail(PCV_ERR_INVALID, "theta is NULL");
+  if (t->cov != PCV_COV_EXP && t->cov != PCV_COV_MATERN32)
+    return fail(PCV_ERR_INVALID, "theta.cov must be PCV_COV_EXP or PCV_COV_MATERN32");
+  if (!(t->range > 0.0) || !is_finite(t->range)) return fail(PCV_ERR_INVALID, "theta.range must be > 0");
+  if (!(t->lambda >= 0.0) || !is_finite(t->lambda)) return fail(PCV_ERR_INVALID, "theta.lambda must be >= 0");
+  if (!(t->sigma2 > 0.0) || !is_finite(t->sigma2)) return fail(PCV_ERR_INVALID, "theta.sigma2 must be > 0");
+  return PCV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pcv_default_options(pcv_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->prec = PCV_PREC_MIXED;
+  opt->max_refine = 1;
+  opt->refine_tol = 1e-12;
+}
+
+const char* pcv_status_string(pcv_status s) {
+  switch (s) {
+    case PCV_OK: return "PCV_OK";
+    case PCV_ERR_INVALID: return "PCV_ERR_INVALID";
+    case PCV_ERR_OOM: return "PCV_ERR_OOM";
+    case PCV_ERR_NOT_PD: return "PCV_ERR_NOT_PD";
+    case PCV_ERR_DEVICE: return "PCV_ERR_DEVICE";
+    case PCV_ERR_STATE: return "PCV_ERR_STATE";
+    case PCV_ERR_BUSY: return "PCV_ERR_BUSY";
+  }
+  return "PCV_ERR_UNKNOWN";
+}
+
+const char* pcv_last_error(void) { return pcv::g_err.c_str(); }
+
+pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs, const double* y,
+                              int32_t S, const int64_t* train_ptr, const int32_t* train_idx,
+                              const int64_t* val_ptr, const int32_t* val_idx, const double* core_rect,
+                              const pcv_options* opt) {
+  pcv::g_err.clear();
+  if (!out) return fail(PCV_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n < 1) return fail(PCV_ERR_INVALID, "n must be >= 1");
+  if (n > INT32_MAX) return fail(PCV_ERR_INVALID, "n must fit in int32 indices");
+  if (!locs || !y) return fail(PCV_ERR_INVALID, "locs and y must be non-NULL");
+  if (S < 1) return fail(PCV_ERR_INVALID, "S must be >= 1");
+  if (!train_ptr || !val_ptr) return fail(PCV_ERR_INVALID, "train_ptr and val_ptr must be non-NULL");
+  if (train_ptr[0] != 0 || val_ptr[0] != 0) return fail(PCV_ERR_INVALID, "ptr arrays must start at 0");
+  for (int32_t i = 0; i < S; ++i) {
+    if (train_ptr[i + 1] < train_ptr[i]) return fail(PCV_ERR_INVALID, "train_ptr decreases at subset " + std::to_string(i));
+    if (val_ptr[i + 1] < val_ptr[i]) return fail(PCV_ERR_INVALID, "val_ptr decreases at subset " + std::to_string(i));
+    if (train_ptr[i + 1] - train_ptr[i] > PCV_MAX_SUBSET)
+      return fail(PCV_ERR_INVALID, "subset " + std::to_string(i) + " has more than PCV_MAX_SUBSET training points");
+  }
+  if ((train_ptr[S] > 0 && !train_idx) || (val_ptr[S] > 0 && !val_idx))
+    return fail(PCV_ERR_INVALID, "index arrays must be non-NULL when non-empty");
+  for (int64_t j = 0; j < train_ptr[S]; ++j)
+    if (train_idx[j] < 0 || train_idx[j] >= n) return fail(PCV_ERR_INVALID, "train_idx[" + std::to_string(j) + "] out of range");
+  for (int64_t j = 0; j < val_ptr[S]; ++j)
+    if (val_idx[j] < 0 || val_idx[j] >= n) return fail(PCV_ERR_INVALID, "val_idx[" + std::to_string(j) + "] out of range");
+  for (int64_t j = 0; j < n; ++j)
+    if (!is_finite(locs[2 * j]) || !is_finite(locs[2 * j + 1]) || !is_finite(y[j]))
+      return fail(PCV_ERR_INVALID, "non-finite location or value at point " + std::to_string(j));
+  if (core_rect)
+    for (int64_t j = 0; j < 4LL * S; ++j)
+      if (!is_finite(core_rect[j])) return fail(PCV_ERR_INVALID, "non-finite core_rect");
+  pcv_options o;
+  pcv_default_options(&o);
+  if (opt) o = *opt;
+  if (o.prec != PCV_PREC_FP64 && o.prec != PCV_PREC_MIXED) return fail(PCV_ERR_INVALID, "opt.prec invalid");
+  if (o.max_refine < 0 || o.max_refine > 8) return fail(PCV_ERR_INVALID, "opt.max_refine must be in [0, 8]");
+  if (!(o.refine_tol >= 0.0)) return fail(PCV_ERR_INVALID, "opt.refine_tol must be >= 0");
+
+  pcv_problem* p = new pcv_problem();
+  p->opt = o;
+  pcv_status st = pcv::problem_build(p, n, locs, y, S, train_ptr, train_idx, val_ptr, val_idx, core_rect);
+  if (st != PCV_OK) {
+    std::string keep = pcv::g_err;
+    pcv::problem_free(p);
+    pcv::g_err = keep;
+    return st;
+  }
+  *out = p;
+  return PCV_OK;
+}
+
+pcv_status pcv_problem_destroy(pcv_problem* p) {
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  pcv::problem_free(p);
+  return PCV_OK;
+}
+
+pcv_status pcv_problem_info(const pcv_problem* p, int32_t* S, int64_t* nnz_train, int32_t* max_train,
+                            size_t* device_bytes) {
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (S) *S = p->S;
+  if (nnz_train) *nnz_train = p->nnzT;
+  if (max_train) *max_train = p->max_train;
+  if (device_bytes) *device_bytes = p->dev_bytes;
+  return PCV_OK;
+}
+
+pcv_status pcv_eval(pcv_problem* p, const pcv_theta* theta, double* loss, pcv_eval_report* report) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (!loss) return fail(PCV_ERR_INVALID, "loss is NULL");
+  pcv_status s = check_theta(theta);
+  if (s != PCV_OK) return s;
+  return pcv::eval_impl(p, *theta, loss, report);
+}
+
+pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (n_theta < 0 || (n_theta > 0 && (!thetas || !losses))) return fail(PCV_ERR_INVALID, "bad batch arguments");
+  for (int32_t k = 0; k < n_theta; ++k) {
+    pcv_status s = check_theta(&thetas[k]);
+    if (s != PCV_OK) return fail(s, "theta[" + std::to_string(k) + "]: " + pcv::g_err);
+  }
+  for (int32_t k = 0; k < n_theta; ++k) {
+    pcv_status s = pcv::eval_impl(p, thetas[k], &losses[k], nullptr);
+    if (s != PCV_OK) return s;
+  }
+  return PCV_OK;
+}
+
+pcv_status pcv_factor(pcv_problem* p, const pcv_theta* theta) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  pcv_status s = check_theta(theta);
+  if (s != PCV_OK) return s;
+  return pcv::factor_impl(p, *theta);
+}
+
+pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
+                       int32_t obs_noise, int32_t* owner) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (q < 0 || (q > 0 && (!qlocs || !mean))) return fail(PCV_ERR_INVALID, "bad query arguments");
+  for (int64_t j = 0; j < 2 * q; ++j)
+    if (!is_finite(qlocs[j])) return fail(PCV_ERR_INVALID, "non-finite query location");
+  if (!p->factored) return fail(PCV_ERR_STATE, "pcv_predict called before pcv_factor");
+  return pcv::predict_impl(p, q, qlocs, mean, var, obs_noise, owner);
+}
+
+}  // extern "C"

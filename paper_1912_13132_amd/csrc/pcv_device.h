@@ -1,0 +1,97 @@
+// Shared definitions of the device path (kernels and their host launchers).
+// gfx950 only: 64-wide wavefronts, MFMA 16x16x4 for FP32 and FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcv {
+
+// Tile / block size of the blocked factorisation and of the solves.  Every
+// subset is padded to a multiple of TB with identity rows (covariance 1 on
+// the diagonal, 0 elsewhere, right-hand side 0), which leaves the real
+// part of every result unchanged.
+constexpr int TB = 64;
+// Rows of one panel chunk in the factorisation: 4 waves x 64 rows.
+constexpr int CHUNK = 256;
+
+// Per-subset descriptor.  Offsets are element offsets into the packed
+// device arrays.
+struct SubsetDesc {
+  int64_t offT;    // training panel (coordinates, y_T)          [n]
+  int64_t offV;    // validation panel (coordinates, y_V, errors) [m]
+  int64_t offP;    // padded vectors (z, alpha, r, x)              [npad]
+  int64_t offL;    // packed tile-row lower factor                 [packed_size(npad)]
+  int64_t offInv;  // inverse diagonal blocks, FP64                [npad * TB]
+  int32_t n, m, npad, id;
+};
+
+// The evaluated parameters, read by every kernel from device memory so that
+// one captured sequence serves any theta.
+struct ThetaDev {
+  int32_t cov;
+  int32_t pad;
+  double range;
+  double inv_range;
+  double lambda;
+  double sigma2;
+};
+
+// Packed tile-row lower storage: row r of block I = r / TB holds columns
+// [0, (I+1) TB) contiguously.  Row-major inside a block row, so any
+// segment of a row that lies on or below the diagonal block is contiguous.
+__host__ __device__ inline int64_t packed_rowoff(int r) {
+  const int64_t I = r / TB;
+  return (int64_t)TB * TB * (I * (I + 1) / 2) + (int64_t)(r % TB) * (I + 1) * TB;
+}
+__host__ __device__ inline int64_t packed_size(int npad) {
+  const int64_t nb = npad / TB;
+  return (int64_t)TB * TB * (nb * (nb + 1) / 2);
+}
+
+}  // namespace pcv
+
+// Host-side launchers implemented in pcv_kernels.hip.
+namespace pcv {
+struct Launch {
+  hipStream_t stream;
+  const SubsetDesc* desc;
+  const ThetaDev* theta;
+};
+hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, const float* cx,
+                            const float* cy, float* Lbuf, double* Inv, double* logdet,
+                            int32_t* status);
+hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
+                            const double* cy, double* Lbuf, double* Inv, double* logdet,
+                            int32_t* status);
+hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, const float* Lbuf,
+                               const double* Inv, const double* rhs_train, const double* rhs_pad,
+                               double* z, double* rhs2);
+hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, const double* Lbuf,
+                               const double* Inv, const double* rhs_train, const double* rhs_pad,
+                               double* z, double* rhs2);
+hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, const float* Lbuf,
+                               const double* Inv, const double* z, double* x, double* alpha_accum);
+hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, const double* Lbuf,
+                               const double* Inv, const double* z, double* x, double* alpha_accum);
+hipError_t launch_residual(const Launch& L, const int2* items, int n_items, const double* tx,
+                           const double* ty, const double* yT, const double* alpha, double* r);
+hipError_t launch_predict_val(const Launch& L, const int2* items, int n_items, const double* tx,
+                              const double* ty, const double* vx, const double* vy,
+                              const double* yV, const double* alpha, double* yhat, double* err);
+// Kriging of query points from resident FP64 factors (mean and variance).
+struct KrigeItem {
+  int32_t sidx;    // subset
+  int32_t q0;      // first query (in the grouped query arrays)
+  int32_t nq;      // queries in this item (<= 64)
+  int32_t pad;
+  int64_t woff;    // scratch offset (npad x 64 doubles)
+};
+hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* theta,
+                        const KrigeItem* items, int n_items, const double* tx, const double* ty,
+                        const double* L64, const double* Inv, const double* alpha, const double* qx,
+                        const double* qy, const int32_t* qorig, double* Wscratch, double* mean,
+                        double* var, int32_t want_var, int32_t obs_noise);
+hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, const double* err,
+                         const int32_t* status, const int32_t* active, double* per_subset_sspe,
+                         double* out_total, int32_t* out_nbad);
+}  // namespace pcv

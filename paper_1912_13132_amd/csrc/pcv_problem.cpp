@@ -1,0 +1,589 @@
+// Problem residency and the evaluation / factorisation / prediction
+// sequences behind the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pcv_host.h"
+
+using pcv::fail;
+using pcv::SubsetDesc;
+using pcv::TB;
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,                \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+namespace pcv {
+namespace {
+
+template <typename T>
+pcv_status dalloc(pcv_problem* p, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  const size_t bytes = count * sizeof(T);
+  if (p->opt.mem_cap_bytes && p->dev_bytes + bytes > p->opt.mem_cap_bytes)
+    return fail(PCV_ERR_OOM, "device memory cap exceeded (" + std::to_string(p->dev_bytes + bytes) +
+                                 " > " + std::to_string(p->opt.mem_cap_bytes) + " bytes)");
+  hipError_t e = hipMalloc((void**)ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,
+                std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  }
+  p->dev_bytes += bytes;
+  p->allocs.push_back((void*)*ptr);
+  return PCV_OK;
+}
+
+template <typename T>
+pcv_status upload(pcv_problem* p, T** dst, const std::vector<T>& src) {
+  pcv_status s = dalloc(p, dst, src.size());
+  if (s != PCV_OK) return s;
+  if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return PCV_OK;
+}
+
+void dfree(pcv_problem* p, void* ptr, size_t bytes) {
+  if (!ptr) return;
+  (void)hipFree(ptr);
+  p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), ptr), p->allocs.end());
+  p->dev_bytes -= bytes;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+pcv_status set_theta(pcv_problem* p, const pcv_theta& th) {
+  ThetaDev* h = p->h_theta;
+  h->cov = th.cov;
+  h->pad = 0;
+  h->range = th.range;
+  h->inv_range = 1.0 / th.range;
+  h->lambda = th.lambda;
+  h->sigma2 = th.sigma2;
+  HIPCHK(hipMemcpyAsync(p->d_theta, h, sizeof(ThetaDev), hipMemcpyHostToDevice, p->stream));
+  return PCV_OK;
+}
+
+pcv_status ensure_L(pcv_problem* p, bool fp64) {
+  if (fp64 && !p->d_L64) return dalloc(p, &p->d_L64, (size_t)p->nL);
+  if (!fp64 && !p->d_L32) return dalloc(p, &p->d_L32, (size_t)p->nL);
+  return PCV_OK;
+}
+
+// Largest n^3 first (longest-processing-time order), ties by index.
+std::vector<int32_t> lpt_order(const std::vector<SubsetDesc>& d, const std::vector<int32_t>& ids) {
+  std::vector<int32_t> o = ids;
+  std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return d[a].npad > d[b].npad; });
+  return o;
+}
+
+// Route queries to cores: half-open [lo, hi) per axis, edges on the domain
+// maximum closed, lowest index first; a point in no core goes to the
+// nearest core rectangle.  Without rectangles: nearest training centroid.
+void route(const pcv_problem* p, int64_t q, const double* ql, std::vector<int32_t>& owner) {
+  owner.assign(q, 0);
+  const int S = p->S;
+  if (!p->core_rect.empty()) {
+    const double* R = p->core_rect.data();
+    double xmax = -INFINITY, ymax = -INFINITY, xmin = INFINITY, ymin = INFINITY;
+    for (int i = 0; i < S; ++i) {
+      xmax = std::max(xmax, R[4 * i + 2]);
+      ymax = std::max(ymax, R[4 * i + 3]);
+      xmin = std::min(xmin, R[4 * i + 0]);
+      ymin = std::min(ymin, R[4 * i + 1]);
+    }
+    // uniform bucket grid over the domain listing the cores that touch each bucket
+    const int G = std::max(1, std::min(512, (int)std::sqrt((double)S) * 2));
+    const double bw = (xmax - xmin) / G, bh = (ymax - ymin) / G;
+    std::vector<std::vector<int32_t>> buckets((size_t)G * G);
+    auto bx = [&](double x) { return std::min(G - 1, std::max(0, (int)std::floor((x - xmin) / bw))); };
+    auto by = [&](double y) { return std::min(G - 1, std::max(0, (int)std::floor((y - ymin) / bh))); };
+    for (int i = 0; i < S; ++i) {
+      const int x0 = bx(R[4 * i]), x1 = bx(R[4 * i + 2]), y0 = by(R[4 * i + 1]), y1 = by(R[4 * i + 3]);
+      for (int yy = y0; yy <= y1; ++yy)
+        for (int xx = x0; xx <= x1; ++xx) buckets[(size_t)yy * G + xx].push_back(i);
+    }
+    for (int64_t j = 0; j < q; ++j) {
+      const double x = ql[2 * j], y = ql[2 * j + 1];
+      int hit = -1;
+      if (x >= xmin && x <= xmax && y >= ymin && y <= ymax && bw > 0 && bh > 0) {
+        for (int32_t i : buckets[(size_t)by(y) * G + bx(x)]) {
+          const double* r = R + 4 * i;
+          const bool inx = x >= r[0] && (x < r[2] || (x == r[2] && r[2] == xmax));
+          const bool iny = y >= r[1] && (y < r[3] || (y == r[3] && r[3] == ymax));
+          if (inx && iny && (hit < 0 || i < hit)) hit = i;
+        }
+      }
+      if (hit < 0) {
+        double best = INFINITY;
+        for (int i = 0; i < S; ++i) {
+          const double* r = R + 4 * i;
+          const double dx = std::max(std::max(r[0] - x, 0.0), x - r[2]);
+          const double dy = std::max(std::max(r[1] - y, 0.0), y - r[3]);
+          const double d2 = dx * dx + dy * dy;
+          if (d2 < best) {
+            best = d2;
+            hit = i;
+          }
+        }
+      }
+      owner[j] = hit;
+    }
+  } else {
+    for (int64_t j = 0; j < q; ++j) {
+      double best = INFINITY;
+      int hit = 0;
+      for (int i = 0; i < S; ++i) {
+        if (p->desc[i].n == 0) continue;
+        const double dx = ql[2 * j] - p->centroid[2 * i], dy = ql[2 * j + 1] - p->centroid[2 * i + 1];
+        const double d2 = dx * dx + dy * dy;
+        if (d2 < best) {
+          best = d2;
+          hit = i;
+        }
+      }
+      owner[j] = hit;
+    }
+  }
+}
+
+}  // namespace
+
+pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const double* y, int32_t S,
+                         const int64_t* tptr, const int32_t* tidx, const int64_t* vptr,
+                         const int32_t* vidx, const double* core_rect) {
+  HIPCHK(hipGetDevice(&p->device));
+  if (p->opt.hip_stream) {
+    p->stream = (hipStream_t)p->opt.hip_stream;
+    p->own_stream = false;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    p->own_stream = true;
+  }
+  p->n = n;
+  p->S = S;
+  p->desc.resize(S);
+  p->active.assign(S, 0);
+  p->centroid.assign(2 * (size_t)S, 0.0);
+  p->ynorm2.assign(S, 0.0);
+  if (core_rect) p->core_rect.assign(core_rect, core_rect + 4 * (size_t)S);
+
+  int64_t offT = 0, offV = 0, offP = 0, offL = 0, offInv = 0;
+  std::vector<int32_t> act_ids, all_ids;
+  for (int32_t i = 0; i < S; ++i) {
+    SubsetDesc& d = p->desc[i];
+    d.n = (int32_t)(tptr[i + 1] - tptr[i]);
+    d.m = (int32_t)(vptr[i + 1] - vptr[i]);
+    d.npad = (d.n + TB - 1) / TB * TB;
+    d.id = i;
+    d.offT = offT;
+    d.offV = offV;
+    d.offP = offP;
+    d.offL = offL;
+    d.offInv = offInv;
+    offT += d.n;
+    offV += d.m;
+    offP += d.npad;
+    offL += packed_size(d.npad);
+    offInv += (int64_t)d.npad * TB;
+    p->max_train = std::max(p->max_train, d.n);
+    if (d.m > 0) {
+      p->active[i] = 1;
+      act_ids.push_back(i);
+      p->n_val_total += d.m;
+    }
+    if (d.n > 0) all_ids.push_back(i);
+  }
+  p->nnzT = offT;
+  p->nnzV = offV;
+  p->nP = offP;
+  p->nL = offL;
+  p->nInv = offInv;
+  p->n_active = (int32_t)act_ids.size();
+  p->order_eval = lpt_order(p->desc, act_ids);
+  p->order_all = lpt_order(p->desc, all_ids);
+  for (int32_t i : p->order_eval) {
+    for (int rb = 0; rb < p->desc[i].npad / TB; ++rb) p->row_items_eval.push_back(make_int2(i, rb));
+    for (int vb = 0; vb < (p->desc[i].m + 63) / 64; ++vb) p->val_items.push_back(make_int2(i, vb));
+  }
+
+  // per-subset panels, centred on the subset's training centroid (FP64)
+  std::vector<double> tx(offT), ty(offT), yT(offT), vx(offV), vy(offV), yV(offV);
+  std::vector<float> tx32(offT), ty32(offT);
+  for (int32_t i = 0; i < S; ++i) {
+    const SubsetDesc& d = p->desc[i];
+    double cx = 0.0, cy = 0.0;
+    if (d.n > 0) {
+      for (int64_t j = tptr[i]; j < tptr[i + 1]; ++j) {
+        cx += locs[2 * (int64_t)tidx[j]];
+        cy += locs[2 * (int64_t)tidx[j] + 1];
+      }
+      cx /= d.n;
+      cy /= d.n;
+    } else if (d.m > 0) {
+      for (int64_t j = vptr[i]; j < vptr[i + 1]; ++j) {
+        cx += locs[2 * (int64_t)vidx[j]];
+        cy += locs[2 * (int64_t)vidx[j] + 1];
+      }
+      cx /= d.m;
+      cy /= d.m;
+    }
+    p->centroid[2 * i] = cx;
+    p->centroid[2 * i + 1] = cy;
+    double y2 = 0.0;
+    for (int64_t j = tptr[i], a = 0; j < tptr[i + 1]; ++j, ++a) {
+      const int64_t g = tidx[j];
+      tx[d.offT + a] = locs[2 * g] - cx;
+      ty[d.offT + a] = locs[2 * g + 1] - cy;
+      tx32[d.offT + a] = (float)tx[d.offT + a];
+      ty32[d.offT + a] = (float)ty[d.offT + a];
+      yT[d.offT + a] = y[g];
+      y2 += y[g] * y[g];
+    }
+    p->ynorm2[i] = y2;
+    for (int64_t j = vptr[i], a = 0; j < vptr[i + 1]; ++j, ++a) {
+      const int64_t g = vidx[j];
+      vx[d.offV + a] = locs[2 * g] - cx;
+      vy[d.offV + a] = locs[2 * g + 1] - cy;
+      yV[d.offV + a] = y[g];
+    }
+  }
+
+  pcv_status s;
+#define TRY(x)              \
+  do {                      \
+    s = (x);                \
+    if (s != PCV_OK) return s; \
+  } while (0)
+  TRY(upload(p, &p->d_desc, p->desc));
+  TRY(upload(p, &p->d_order_eval, p->order_eval));
+  TRY(upload(p, &p->d_order_all, p->order_all));
+  TRY(upload(p, &p->d_active, p->active));
+  TRY(upload(p, &p->d_row_items, p->row_items_eval));
+  TRY(upload(p, &p->d_val_items, p->val_items));
+  TRY(upload(p, &p->d_tx, tx));
+  TRY(upload(p, &p->d_ty, ty));
+  TRY(upload(p, &p->d_yT, yT));
+  TRY(upload(p, &p->d_tx32, tx32));
+  TRY(upload(p, &p->d_ty32, ty32));
+  TRY(upload(p, &p->d_vx, vx));
+  TRY(upload(p, &p->d_vy, vy));
+  TRY(upload(p, &p->d_yV, yV));
+  TRY(dalloc(p, &p->d_z, (size_t)p->nP));
+  TRY(dalloc(p, &p->d_x, (size_t)p->nP));
+  TRY(dalloc(p, &p->d_alpha, (size_t)p->nP));
+  TRY(dalloc(p, &p->d_r, (size_t)p->nP));
+  TRY(dalloc(p, &p->d_rhs2, (size_t)S));
+  TRY(dalloc(p, &p->d_yhat, (size_t)p->nnzV));
+  TRY(dalloc(p, &p->d_err, (size_t)p->nnzV));
+  TRY(dalloc(p, &p->d_logdet, (size_t)S));
+  TRY(dalloc(p, &p->d_sspe, (size_t)S));
+  TRY(dalloc(p, &p->d_status, (size_t)S));
+  TRY(dalloc(p, &p->d_theta, 1));
+  TRY(dalloc(p, &p->d_total, 1));
+  TRY(dalloc(p, &p->d_nbad, 1));
+  TRY(dalloc(p, &p->d_Inv, (size_t)p->nInv));
+#undef TRY
+  HIPCHK(hipMemset(p->d_status, 0, sizeof(int32_t) * S));
+  HIPCHK(hipMemset(p->d_logdet, 0, sizeof(double) * S));
+  HIPCHK(hipHostMalloc((void**)&p->h_theta, sizeof(ThetaDev), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&p->h_total, sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&p->h_nbad, sizeof(int32_t), hipHostMallocDefault));
+  if (p->opt.profile) {
+    for (auto& e : p->ev) HIPCHK(hipEventCreate(&e));
+    p->events = true;
+  }
+  return PCV_OK;
+}
+
+void problem_free(pcv_problem* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+  if (p->h_theta) (void)hipHostFree(p->h_theta);
+  if (p->h_total) (void)hipHostFree(p->h_total);
+  if (p->h_nbad) (void)hipHostFree(p->h_nbad);
+  if (p->events)
+    for (auto& e : p->ev) (void)hipEventDestroy(e);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+namespace {
+
+// Factor + solve alpha = M^{-1} y_T in FP64 for the subsets in `d_order`
+// (device list of `count` subset ids) into the given buffers.
+pcv_status factor_solve64(pcv_problem* p, const ThetaDev* d_theta, const int32_t* d_order, int count,
+                          double* Lb, double* Invb, double* zb, double* alphab, double* logdetb,
+                          int32_t* statusb) {
+  Launch Lc{p->stream, p->d_desc, d_theta};
+  HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_tx, p->d_ty, Lb, Invb, logdetb, statusb));
+  HIPCHK(launch_trsv_fwd_f64(Lc, d_order, count, Lb, Invb, p->d_yT, nullptr, zb, nullptr));
+  HIPCHK(launch_trsv_bwd_f64(Lc, d_order, count, Lb, Invb, zb, alphab, nullptr));
+  return PCV_OK;
+}
+
+}  // namespace
+
+pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep) {
+  const double t0 = now_s();
+  HIPCHK(hipSetDevice(p->device));
+  const bool mixed = p->opt.prec == PCV_PREC_MIXED;
+  pcv_status s = ensure_L(p, !mixed);
+  if (s != PCV_OK) return s;
+  s = set_theta(p, th);
+  if (s != PCV_OK) return s;
+  Launch Lc{p->stream, p->d_desc, p->d_theta};
+  const bool ev = p->events;
+  if (ev) HIPCHK(hipEventRecord(p->ev[0], p->stream));
+  if (mixed)
+    HIPCHK(launch_potrf_f32(Lc, p->d_order_eval, p->n_active, p->d_tx32, p->d_ty32, p->d_L32, p->d_Inv,
+                            p->d_logdet, p->d_status));
+  else
+    HIPCHK(launch_potrf_f64(Lc, p->d_order_eval, p->n_active, p->d_tx, p->d_ty, p->d_L64, p->d_Inv,
+                            p->d_logdet, p->d_status));
+  if (ev) HIPCHK(hipEventRecord(p->ev[1], p->stream));
+  if (mixed) {
+    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, p->d_yT, nullptr, p->d_z,
+                               nullptr));
+    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, p->d_z, p->d_alpha,
+                               nullptr));
+  } else {
+    HIPCHK(launch_trsv_fwd_f64(Lc, p->d_order_eval, p->n_active, p->d_L64, p->d_Inv, p->d_yT, nullptr, p->d_z,
+                               nullptr));
+    HIPCHK(launch_trsv_bwd_f64(Lc, p->d_order_eval, p->n_active, p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
+                               nullptr));
+  }
+  if (ev) HIPCHK(hipEventRecord(p->ev[2], p->stream));
+  const int sweeps = mixed ? p->opt.max_refine : 0;
+  for (int it = 0; it < sweeps; ++it) {
+    HIPCHK(launch_residual(Lc, p->d_row_items, (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT,
+                           p->d_alpha, p->d_r));
+    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, nullptr, p->d_r, p->d_z,
+                               p->d_rhs2));
+    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, p->d_z, p->d_x,
+                               p->d_alpha));
+  }
+  if (ev) HIPCHK(hipEventRecord(p->ev[3], p->stream));
+  HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx, p->d_vy,
+                            p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
+  if (ev) HIPCHK(hipEventRecord(p->ev[4], p->stream));
+  HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, p->d_sspe, p->d_total,
+                       p->d_nbad));
+  if (ev) HIPCHK(hipEventRecord(p->ev[5], p->stream));
+  HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+
+  int32_t n_fallback = 0;
+  const bool force_fb = mixed && (p->opt.debug_flags & 1) && p->n_active > 0;
+  if (*p->h_nbad > 0 || force_fb) {
+    std::vector<int32_t> status(p->S);
+    HIPCHK(hipMemcpy(status.data(), p->d_status, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost));
+    std::vector<int32_t> bad;
+    for (int32_t i : p->order_eval)
+      if (status[i] || force_fb) bad.push_back(i);
+    if (!mixed) {
+      return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(bad[0]) + " is not positive definite (pivot " +
+                                      std::to_string(status[bad[0]] - 1) + ")");
+    }
+    // FP64 re-run of the subsets whose FP32 factorisation broke down
+    n_fallback = (int32_t)bad.size();
+    s = ensure_L(p, true);
+    if (s != PCV_OK) return s;
+    int32_t* d_bad = nullptr;
+    HIPCHK(hipMalloc((void**)&d_bad, sizeof(int32_t) * bad.size()));
+    HIPCHK(hipMemcpy(d_bad, bad.data(), sizeof(int32_t) * bad.size(), hipMemcpyHostToDevice));
+    s = factor_solve64(p, p->d_theta, d_bad, (int)bad.size(), p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
+                       p->d_logdet, p->d_status);
+    if (s == PCV_OK) {
+      HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
+                                p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
+      HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, p->d_sspe,
+                           p->d_total, p->d_nbad));
+      HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+    }
+    (void)hipFree(d_bad);
+    if (s != PCV_OK) return s;
+    if (*p->h_nbad > 0) {
+      HIPCHK(hipMemcpy(status.data(), p->d_status, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost));
+      for (int32_t i : bad)
+        if (status[i])
+          return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(i) + " is not positive definite in FP64");
+    }
+  }
+  *loss = *p->h_total;
+  if (rep) {
+    rep->sspe = *loss;
+    rep->n_val = p->n_val_total;
+    rep->mse = p->n_val_total ? *loss / (double)p->n_val_total : 0.0;
+    rep->n_subsets_used = p->n_active;
+    rep->n_fallback_fp64 = n_fallback;
+    rep->max_refine_iters = sweeps;
+    rep->max_rel_residual = 0.0;
+    if (sweeps > 0) {
+      std::vector<double> r2(p->S);
+      HIPCHK(hipMemcpy(r2.data(), p->d_rhs2, sizeof(double) * p->S, hipMemcpyDeviceToHost));
+      for (int32_t i : p->order_eval)
+        if (p->ynorm2[i] > 0) rep->max_rel_residual = std::max(rep->max_rel_residual, std::sqrt(r2[i] / p->ynorm2[i]));
+    }
+    if (rep->per_subset_sspe)
+      HIPCHK(hipMemcpy(rep->per_subset_sspe, p->d_sspe, sizeof(double) * p->S, hipMemcpyDeviceToHost));
+    if (rep->per_subset_logdet) {
+      std::vector<double> ld(p->S);
+      HIPCHK(hipMemcpy(ld.data(), p->d_logdet, sizeof(double) * p->S, hipMemcpyDeviceToHost));
+      for (int32_t i = 0; i < p->S; ++i) rep->per_subset_logdet[i] = p->active[i] ? ld[i] : 0.0;
+    }
+    if (rep->per_subset_iters)
+      for (int32_t i = 0; i < p->S; ++i) rep->per_subset_iters[i] = p->active[i] ? sweeps : 0;
+    rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
+    if (ev) {
+      float ms;
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+      rep->ms_factor = ms;
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[1], p->ev[2]));
+      rep->ms_solve = ms;
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[2], p->ev[3]));
+      rep->ms_refine = ms;
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[3], p->ev[4]));
+      rep->ms_predict = ms;
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[4], p->ev[5]));
+      rep->ms_reduce = ms;
+    }
+    rep->seconds = now_s() - t0;
+  }
+  return PCV_OK;
+}
+
+pcv_status factor_impl(pcv_problem* p, const pcv_theta& th) {
+  HIPCHK(hipSetDevice(p->device));
+  p->factored = false;
+  pcv_status s = PCV_OK;
+  if (!p->d_Lf) {
+    if ((s = dalloc(p, &p->d_Lf, (size_t)p->nL)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_Invf, (size_t)p->nInv)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_alpha_fact, (size_t)p->nP)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_zf, (size_t)p->nP)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_logdetf, (size_t)p->S)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_statusf, (size_t)p->S)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_theta_fact, 1)) != PCV_OK) return s;
+  }
+  ThetaDev h;
+  h.cov = th.cov;
+  h.pad = 0;
+  h.range = th.range;
+  h.inv_range = 1.0 / th.range;
+  h.lambda = th.lambda;
+  h.sigma2 = th.sigma2;
+  HIPCHK(hipMemcpyAsync(p->d_theta_fact, &h, sizeof(ThetaDev), hipMemcpyHostToDevice, p->stream));
+  const int count = (int)p->order_all.size();
+  s = factor_solve64(p, p->d_theta_fact, p->d_order_all, count, p->d_Lf, p->d_Invf, p->d_zf, p->d_alpha_fact,
+                     p->d_logdetf, p->d_statusf);
+  if (s != PCV_OK) return s;
+  std::vector<int32_t> status(p->S);
+  HIPCHK(hipMemcpyAsync(status.data(), p->d_statusf, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (int32_t i : p->order_all)
+    if (status[i]) return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(i) + " is not positive definite in FP64");
+  p->fact_theta = th;
+  p->factored = true;
+  return PCV_OK;
+}
+
+pcv_status predict_impl(pcv_problem* p, int64_t q, const double* ql, double* mean, double* var,
+                        int32_t obs_noise, int32_t* owner_out) {
+  HIPCHK(hipSetDevice(p->device));
+  if (q == 0) return PCV_OK;
+  std::vector<int32_t> owner;
+  route(p, q, ql, owner);
+  if (owner_out) std::copy(owner.begin(), owner.end(), owner_out);
+  // group queries by subset
+  std::vector<int64_t> perm(q);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return owner[a] < owner[b]; });
+  std::vector<double> qx(q), qy(q);
+  std::vector<int32_t> qorig(q);
+  std::vector<KrigeItem> items;
+  int64_t woff = 0;
+  for (int64_t k = 0; k < q;) {
+    const int32_t i = owner[perm[k]];
+    int64_t e = k;
+    while (e < q && owner[perm[e]] == i) ++e;
+    for (int64_t j = k; j < e; ++j) {
+      qx[j] = ql[2 * perm[j]] - p->centroid[2 * i];
+      qy[j] = ql[2 * perm[j] + 1] - p->centroid[2 * i + 1];
+      qorig[j] = (int32_t)perm[j];
+    }
+    for (int64_t j = k; j < e; j += 64) {
+      KrigeItem it;
+      it.sidx = i;
+      it.q0 = (int32_t)j;
+      it.nq = (int32_t)std::min<int64_t>(64, e - j);
+      it.pad = 0;
+      it.woff = woff;
+      woff += (int64_t)p->desc[i].npad * 64;
+      items.push_back(it);
+    }
+    k = e;
+  }
+  // transient device buffers for this request
+  double *d_qx = nullptr, *d_qy = nullptr, *d_mean = nullptr, *d_var = nullptr, *d_W = nullptr;
+  int32_t* d_qorig = nullptr;
+  KrigeItem* d_items = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(d_qx);
+    (void)hipFree(d_qy);
+    (void)hipFree(d_mean);
+    (void)hipFree(d_var);
+    (void)hipFree(d_W);
+    (void)hipFree(d_qorig);
+    (void)hipFree(d_items);
+  };
+  hipError_t e = hipSuccess;
+  const bool want_var = var != nullptr;
+  if (e == hipSuccess) e = hipMalloc((void**)&d_qx, sizeof(double) * q);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_qy, sizeof(double) * q);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_mean, sizeof(double) * q);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_var, sizeof(double) * q);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_qorig, sizeof(int32_t) * q);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_items, sizeof(KrigeItem) * items.size());
+  if (e == hipSuccess && want_var) e = hipMalloc((void**)&d_W, sizeof(double) * std::max<int64_t>(woff, 1));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_qx, qx.data(), sizeof(double) * q, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_qy, qy.data(), sizeof(double) * q, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_qorig, qorig.data(), sizeof(int32_t) * q, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_items, items.data(), sizeof(KrigeItem) * items.size(), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = launch_krige(p->stream, p->d_desc, p->d_theta_fact, d_items, (int)items.size(), p->d_tx, p->d_ty,
+                     p->d_Lf, p->d_Invf, p->d_alpha_fact, d_qx, d_qy, d_qorig, d_W, d_mean, d_var, want_var ? 1 : 0,
+                     obs_noise);
+  if (e == hipSuccess) e = hipMemcpyAsync(mean, d_mean, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && want_var)
+    e = hipMemcpyAsync(var, d_var, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  cleanup();
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,
+                std::string("predict: ") + hipGetErrorString(e));
+  return PCV_OK;
+}
+
+}  // namespace pcv

@@ -1,0 +1,234 @@
+"""ctypes binding of libpcv.so (the C ABI declared in include/pcv.h).
+
+Argument marshalling only: every step of an evaluation or a prediction runs
+in the library's HIP kernels.  The library must have been built
+(``paper_1912_13132_amd.build.build()``); there is no fallback path, so a
+missing library raises at first use.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcv.so")
+
+PCV_OK = 0
+STATUS = {0: "PCV_OK", 1: "PCV_ERR_INVALID", 2: "PCV_ERR_OOM", 3: "PCV_ERR_NOT_PD",
+          4: "PCV_ERR_DEVICE", 5: "PCV_ERR_STATE", 6: "PCV_ERR_BUSY"}
+COV_EXP = 0
+COV_MATERN32 = 1
+PREC_FP64 = 0
+PREC_MIXED = 1
+MAX_SUBSET = 16384
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+_c_int64_p = ctypes.POINTER(ctypes.c_int64)
+
+
+class PcvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Theta(ctypes.Structure):
+    _fields_ = [("cov", ctypes.c_int32), ("range", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("sigma2", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
+                ("mem_cap_bytes", ctypes.c_size_t), ("profile", ctypes.c_int32),
+                ("debug_flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class EvalReport(ctypes.Structure):
+    _fields_ = [("sspe", ctypes.c_double), ("n_val", ctypes.c_int64), ("mse", ctypes.c_double),
+                ("n_subsets_used", ctypes.c_int32), ("n_fallback_fp64", ctypes.c_int32),
+                ("max_refine_iters", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("max_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("ms_factor", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("ms_refine", ctypes.c_double), ("ms_predict", ctypes.c_double),
+                ("ms_reduce", ctypes.c_double),
+                ("per_subset_sspe", _c_double_p), ("per_subset_logdet", _c_double_p),
+                ("per_subset_iters", _c_int32_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpcv.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1912_13132_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.pcv_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.pcv_default_options.restype = None
+    L.pcv_problem_create.argtypes = [ctypes.POINTER(P), ctypes.c_int64, _c_double_p, _c_double_p,
+                                     ctypes.c_int32, _c_int64_p, _c_int32_p, _c_int64_p, _c_int32_p,
+                                     _c_double_p, ctypes.POINTER(Options)]
+    L.pcv_eval.argtypes = [P, ctypes.POINTER(Theta), _c_double_p, ctypes.POINTER(EvalReport)]
+    L.pcv_eval_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p]
+    L.pcv_factor.argtypes = [P, ctypes.POINTER(Theta)]
+    L.pcv_predict.argtypes = [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
+                              ctypes.c_int32, _c_int32_p]
+    L.pcv_problem_destroy.argtypes = [P]
+    L.pcv_problem_info.argtypes = [P, _c_int32_p, _c_int64_p, _c_int32_p,
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    L.pcv_status_string.argtypes = [ctypes.c_int]
+    L.pcv_status_string.restype = ctypes.c_char_p
+    L.pcv_last_error.argtypes = []
+    L.pcv_last_error.restype = ctypes.c_char_p
+    for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
+              "pcv_problem_destroy", "pcv_problem_info"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != PCV_OK:
+        raise PcvError(st, lib().pcv_last_error().decode())
+
+
+def theta(range_, lam, cov=COV_EXP, sigma2=1.0):
+    return Theta(int(cov), float(range_), float(lam), float(sigma2))
+
+
+def _as(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):      # torch.cuda.Stream
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+class Problem:
+    """A divided problem resident on the current HIP device (Algorithm 1,
+    steps 2-5: divide and read once, evaluate many zeta)."""
+
+    def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
+                 prec="mixed", max_refine=1, refine_tol=1e-12, stream=None, mem_cap=0,
+                 profile=False, debug_flags=0):
+        L = lib()
+        self._locs = _as(locs, np.float64).reshape(-1, 2)
+        self._y = _as(y, np.float64)
+        self._tp = _as(train_ptr, np.int64)
+        self._ti = _as(train_idx, np.int32)
+        self._vp = _as(val_ptr, np.int64)
+        self._vi = _as(val_idx, np.int32)
+        self._rect = None if core_rect is None else _as(core_rect, np.float64).reshape(-1, 4)
+        self.S = int(self._tp.shape[0] - 1)
+        opt = Options()
+        L.pcv_default_options(ctypes.byref(opt))
+        opt.prec = PREC_MIXED if prec == "mixed" else PREC_FP64
+        opt.max_refine = int(max_refine)
+        opt.refine_tol = float(refine_tol)
+        opt.hip_stream = _stream_handle(stream)
+        opt.mem_cap_bytes = int(mem_cap)
+        opt.profile = 1 if profile else 0
+        opt.debug_flags = int(debug_flags)
+        self.prec = prec
+        h = ctypes.c_void_p()
+        _check(L.pcv_problem_create(
+            ctypes.byref(h), self._locs.shape[0], _ptr(self._locs, ctypes.c_double),
+            _ptr(self._y, ctypes.c_double), self.S, _ptr(self._tp, ctypes.c_int64),
+            _ptr(self._ti, ctypes.c_int32), _ptr(self._vp, ctypes.c_int64),
+            _ptr(self._vi, ctypes.c_int32),
+            None if self._rect is None else _ptr(self._rect, ctypes.c_double), ctypes.byref(opt)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        pt = w.part
+        return cls(w.locs, w.y, pt.train_ptr, pt.train_idx, pt.val_ptr, pt.val_idx,
+                   core_rect=pt.core_rect, **kw)
+
+    def _handle(self):
+        if self._h is None:
+            raise PcvError(1, "problem destroyed")
+        return self._h
+
+    def eval(self, th, report=False):
+        """One theta-evaluation; returns the loss (SSPE, eq. (7)), or
+        (loss, report dict) when report=True."""
+        L = lib()
+        loss = ctypes.c_double()
+        if not report:
+            _check(L.pcv_eval(self._handle(), ctypes.byref(th), ctypes.byref(loss), None))
+            return loss.value
+        rep = EvalReport()
+        z = np.zeros(self.S)
+        ld = np.zeros(self.S)
+        it = np.zeros(self.S, dtype=np.int32)
+        rep.per_subset_sspe = _ptr(z, ctypes.c_double)
+        rep.per_subset_logdet = _ptr(ld, ctypes.c_double)
+        rep.per_subset_iters = _ptr(it, ctypes.c_int32)
+        _check(L.pcv_eval(self._handle(), ctypes.byref(th), ctypes.byref(loss), ctypes.byref(rep)))
+        d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
+             if not k.startswith("per_subset") and k != "pad0"}
+        d.update(per_subset_sspe=z, per_subset_logdet=ld, per_subset_iters=it)
+        return loss.value, d
+
+    def eval_batch(self, thetas):
+        L = lib()
+        arr = (Theta * len(thetas))(*thetas)
+        out = np.zeros(len(thetas))
+        _check(L.pcv_eval_batch(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double)))
+        return out
+
+    def factor(self, th):
+        _check(lib().pcv_factor(self._handle(), ctypes.byref(th)))
+
+    def predict(self, q, want_var=True, obs_noise=False):
+        q = _as(q, np.float64).reshape(-1, 2)
+        nq = q.shape[0]
+        mean = np.zeros(nq)
+        var = np.zeros(nq) if want_var else None
+        owner = np.zeros(nq, dtype=np.int32)
+        _check(lib().pcv_predict(self._handle(), nq, _ptr(q, ctypes.c_double),
+                                 _ptr(mean, ctypes.c_double),
+                                 None if var is None else _ptr(var, ctypes.c_double),
+                                 1 if obs_noise else 0, _ptr(owner, ctypes.c_int32)))
+        return mean, var, owner
+
+    def info(self):
+        S = ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        mx = ctypes.c_int32()
+        b = ctypes.c_size_t()
+        _check(lib().pcv_problem_info(self._handle(), ctypes.byref(S), ctypes.byref(nnz),
+                                      ctypes.byref(mx), ctypes.byref(b)))
+        return dict(S=S.value, nnz_train=nnz.value, max_train=mx.value, device_bytes=b.value)
+
+    def close(self):
+        if self._h is not None:
+            lib().pcv_problem_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

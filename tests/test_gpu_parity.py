@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (relative, on the SSPE of eq. (4) / eq. (7)):
+  FP64 path    1e-10  (the only differences are summation order and
+                       centring of coordinates; both ~1e-14 here)
+  mixed path   1e-6   (FP32 factor, FP64 refinement / prediction / sums)
+Predictions from the resident FP64 factors: mean and variance within 1e-9.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_13132_amd import partition as part
+from paper_1912_13132_amd import pcv
+from paper_1912_13132_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_MIXED = 1e-6
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _rng(k):
+    return np.random.default_rng(np.random.SeedSequence([1912, 13132, 500 + k]))
+
+
+def _oracle(w, th, subsets=None):
+    pt = w.part
+    return oracle.cv_loss(w.locs, w.y, pt.train_ptr, pt.train_idx, pt.val_ptr, pt.val_idx,
+                          th.cov, th.range, th.lambda_, subsets=subsets)
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _check_full(w, th, prec, tol, max_refine=1):
+    say(f"[case] {w.name} N={len(w.y)} S={w.part.n_subsets} prec={prec} "
+        f"theta=({th.range},{th.lambda_},cov={th.cov})")
+    ref = _oracle(w, th)
+    with pcv.Problem.from_workload(w, prec=prec, max_refine=max_refine) as P:
+        loss, rep = P.eval(th, report=True)
+    assert rep["n_val"] == ref["n_val"]
+    assert _rel(loss, ref["sspe"]) <= tol, (loss, ref["sspe"], _rel(loss, ref["sspe"]))
+    z = rep["per_subset_sspe"]
+    zr = ref["per_subset_sspe"]
+    big = zr > 1e-12 * max(zr.max(), 1.0)
+    per = np.abs(z[big] - zr[big]) / zr[big]
+    say(f"   loss rel err {_rel(loss, ref['sspe']):.2e}  max per-subset {per.max() if per.size else 0:.2e}"
+        f"  fallback {rep['n_fallback_fp64']}  max rel residual {rep['max_rel_residual']:.2e}")
+    assert np.all(per <= 100 * tol)
+    assert np.all(z[~big] <= 1e-10)
+    act = ref["per_subset_nval"] > 0
+    np.testing.assert_allclose(rep["per_subset_logdet"][act], ref["per_subset_logdet"][act],
+                               rtol=1e-9 if prec == "fp64" else 1e-4, atol=1e-8)
+    return loss, rep
+
+
+# ------------------------------------------------------------ workloads ---
+@pytest.fixture(scope="module")
+def w_plain():
+    return W.plain_fp64()
+
+
+@pytest.fixture(scope="module")
+def w_batched_small():
+    return W.scaled("batched", 0.05)
+
+
+@pytest.fixture(scope="module")
+def w_uneven_small():
+    return W.scaled("uneven", 0.01)
+
+
+def test_plain_fp64_config_fp64_path(w_plain):
+    _check_full(w_plain, pcv.theta(0.1, 0.05), "fp64", TOL_FP64)
+
+
+def test_plain_fp64_config_mixed_path(w_plain):
+    _check_full(w_plain, pcv.theta(0.1, 0.05), "mixed", TOL_MIXED)
+
+
+@pytest.mark.parametrize("k", [0, 27, 63])
+def test_batched_recipe_theta_grid(w_batched_small, k):
+    g = W.theta_grid(w_batched_small.theta_true, 8)
+    th = pcv.theta(*g[k])
+    _check_full(w_batched_small, th, "fp64", TOL_FP64)
+    _check_full(w_batched_small, th, "mixed", TOL_MIXED)
+
+
+def test_uneven_recipe_matern(w_uneven_small):
+    th = pcv.theta(0.03, 0.02, cov=pcv.COV_MATERN32)
+    _check_full(w_uneven_small, th, "fp64", TOL_FP64)
+    _check_full(w_uneven_small, th, "mixed", TOL_MIXED)
+
+
+# ----------------------------------------------------------- edge cases ---
+def _synthetic(sizes_T, sizes_V, seed, spread=1.0):
+    """Independent subsets with the given training / validation sizes."""
+    r = _rng(seed)
+    locs, y, tl, vl = [], [], [], []
+    off = 0
+    for nt, nv in zip(sizes_T, sizes_V):
+        P = r.uniform(0, spread, (nt + nv, 2))
+        yy = r.standard_normal(nt + nv)
+        locs.append(P)
+        y.append(yy)
+        tl.append(np.arange(off, off + nt))
+        vl.append(np.arange(off + nt, off + nt + nv))
+        off += nt + nv
+    locs = np.concatenate(locs)
+    y = np.concatenate(y)
+    tp = np.r_[0, np.cumsum(sizes_T)]
+    vp = np.r_[0, np.cumsum(sizes_V)]
+    ti = np.concatenate(tl).astype(np.int32)
+    vi = np.concatenate(vl).astype(np.int32)
+    return locs, y, tp, ti, vp, vi
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_ragged_sizes_and_degenerate_subsets(prec, tol):
+    """Sizes around the 64-row tile and the 256-row chunk, n = 1, n = 0 with
+    validation points (prior mean), and subsets without validation points
+    (skipped)."""
+    sizes_T = [1, 2, 63, 64, 65, 127, 128, 255, 256, 257, 300, 513, 0, 40, 77]
+    sizes_V = [3, 5, 7, 1, 9, 11, 13, 2, 4, 6, 30, 50, 4, 0, 8]
+    locs, y, tp, ti, vp, vi = _synthetic(sizes_T, sizes_V, 1)
+    say(f"[case] ragged prec={prec} sizes={sizes_T}")
+    th = pcv.theta(0.3, 0.1)
+    ref = oracle.cv_loss(locs, y, tp, ti, vp, vi, 0, 0.3, 0.1)
+    with pcv.Problem(locs, y, tp, ti, vp, vi, prec=prec) as P:
+        loss, rep = P.eval(th, report=True)
+    assert _rel(loss, ref["sspe"]) <= tol
+    np.testing.assert_allclose(rep["per_subset_sspe"], ref["per_subset_sspe"], rtol=100 * tol, atol=1e-12)
+    assert rep["per_subset_sspe"][13] == 0.0
+    assert rep["n_val"] == ref["n_val"]
+
+
+def test_no_nugget_fp64():
+    """lambda = 0 is allowed (tau >= 0 in eq. (1)); distinct points keep M SPD."""
+    locs, y, tp, ti, vp, vi = _synthetic([120, 90], [10, 10], 2)
+    say("[case] lambda=0 fp64")
+    ref = oracle.cv_loss(locs, y, tp, ti, vp, vi, 0, 0.05, 0.0)
+    with pcv.Problem(locs, y, tp, ti, vp, vi, prec="fp64") as P:
+        loss = P.eval(pcv.theta(0.05, 0.0))
+    assert _rel(loss, ref["sspe"]) <= 1e-8
+
+
+def test_not_positive_definite_is_reported():
+    """Duplicate training locations with lambda = 0 make M singular: the FP64
+    path reports PCV_ERR_NOT_PD naming the subset."""
+    locs = np.array([[0.1, 0.1], [0.1, 0.1], [0.5, 0.5], [0.2, 0.3]])
+    y = np.array([1.0, 1.0, 0.5, 0.2])
+    say("[case] not PD")
+    with pcv.Problem(locs, y, [0, 3], [0, 1, 2], [0, 1], [3], prec="fp64") as P:
+        with pytest.raises(pcv.PcvError) as e:
+            P.eval(pcv.theta(0.2, 0.0))
+        assert e.value.status == 3
+        # the same problem with a nugget is fine
+        ref = oracle.cv_loss(locs, y, [0, 3], [0, 1, 2], [0, 1], [3], 0, 0.2, 0.1)
+        assert _rel(P.eval(pcv.theta(0.2, 0.1)), ref["sspe"]) <= TOL_FP64
+
+
+def test_mixed_fallback_path(w_plain):
+    """The FP64 re-run that replaces a broken-down FP32 factorisation,
+    forced for every subset from the host: identical to the FP64 path."""
+    th = pcv.theta(0.1, 0.05)
+    say("[case] forced mixed -> fp64 fallback")
+    with pcv.Problem.from_workload(w_plain, prec="mixed", debug_flags=1) as P:
+        loss, rep = P.eval(th, report=True)
+    with pcv.Problem.from_workload(w_plain, prec="fp64") as P:
+        ref = P.eval(th)
+    assert rep["n_fallback_fp64"] == rep["n_subsets_used"] == w_plain.part.n_subsets
+    assert loss == ref
+
+
+def test_repeatable_bitwise(w_batched_small):
+    """Two evaluations of the same theta are bitwise equal (fixed-order sums)."""
+    th = pcv.theta(0.05, 0.1)
+    with pcv.Problem.from_workload(w_batched_small, prec="mixed") as P:
+        a = P.eval(th)
+        P.eval(pcv.theta(0.03, 0.2))
+        b = P.eval(th)
+    assert a == b
+
+
+def test_eval_batch_matches_single(w_plain):
+    g = W.theta_grid(w_plain.theta_true, 3)
+    ths = [pcv.theta(*t) for t in g]
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        batch = P.eval_batch(ths)
+        single = [P.eval(t) for t in ths]
+    np.testing.assert_array_equal(batch, single)
+
+
+# ------------------------------------------------------------ prediction --
+def test_predict_matches_oracle(w_plain):
+    th = pcv.theta(0.1, 0.05, sigma2=1.3)
+    r = _rng(4)
+    q = np.concatenate([r.uniform(0, 1, (300, 2)), [[0.5, 0.5], [1.0, 1.0], [0.0, 0.0], [1.2, -0.1]]])
+    pt = w_plain.part
+    say("[case] predict plain_fp64")
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        with pytest.raises(pcv.PcvError) as e:
+            P.predict(q)
+        assert e.value.status == 5
+        P.factor(th)
+        P.eval(pcv.theta(0.2, 0.3))  # evaluations must not disturb the factors
+        mean, var, owner = P.predict(q)
+        m2, v2, _ = P.predict(q, obs_noise=True)
+    rm, rv, ro = oracle.predict_problem(w_plain.locs, w_plain.y, pt.train_ptr, pt.train_idx,
+                                        pt.core_rect, q, 0, 0.1, 0.05, sigma2=1.3)
+    np.testing.assert_array_equal(owner, ro)
+    np.testing.assert_allclose(mean, rm, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(var, rv, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(v2, rv + 1.3 * 0.05, rtol=1e-9, atol=1e-11)
+    np.testing.assert_array_equal(m2, mean)
+
+
+def test_predict_interpolates_without_nugget():
+    """lambda = 0: predicting at training locations returns the data with
+    zero variance (oracle pin carried to the device path)."""
+    r = _rng(5)
+    locs = r.uniform(0, 1, (150, 2))
+    y = r.standard_normal(150)
+    with pcv.Problem(locs, y, [0, 150], np.arange(150), [0, 0], [], prec="fp64",
+                     core_rect=[[0, 0, 1, 1]]) as P:
+        P.factor(pcv.theta(0.1, 0.0))
+        mean, var, _ = P.predict(locs[::5])
+    np.testing.assert_allclose(mean, y[::5], atol=1e-8)
+    np.testing.assert_allclose(var, 0.0, atol=1e-8)
