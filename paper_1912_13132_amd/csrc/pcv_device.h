@@ -43,6 +43,11 @@ __host__ __device__ inline int64_t packed_rowoff(int r) {
   const int64_t I = r / TB;
   return (int64_t)TB * TB * (I * (I + 1) / 2) + (int64_t)(r % TB) * (I + 1) * TB;
 }
+// 32-bit form for indexing inside one subset (npad <= 16384 keeps it < 2^31).
+__host__ __device__ inline int packed_rowoff32(int r) {
+  const int I = r / TB;
+  return TB * TB * (I * (I + 1) / 2) + (r % TB) * (I + 1) * TB;
+}
 __host__ __device__ inline int64_t packed_size(int npad) {
   const int64_t nb = npad / TB;
   return (int64_t)TB * TB * (nb * (nb + 1) / 2);

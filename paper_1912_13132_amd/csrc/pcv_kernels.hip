@@ -1,10 +1,7 @@
 // Device kernels of one theta-evaluation of the parallel CV loss
 // (Gerber & Nychka, arXiv:1912.13132).
 //
-//   k_potrf<T>      covariance tiles (Sec. 3 / eq. (1)) generated in registers,
-//                   blocked left-looking Cholesky of Sigma + lambda I
-//                   (the (Sigma + lambda I)^{-1} of eq. (3)); tile updates on
-//                   MFMA in T, diagonal blocks factored and inverted in FP64
+//   (the factorisation k_potrf<T> lives in pcv_potrf.hip)
 //   k_trsv_fwd<T>   forward substitution L z = b (FP64 accumulation)
 //   k_trsv_bwd<T>   backward substitution L^T x = z, optionally alpha += x
 //   k_residual      r = y_T - (Sigma + lambda I) alpha in FP64, the matrix
@@ -77,275 +74,6 @@ struct Tile {
   static constexpr int KC = 128 / sizeof(T);
   static constexpr int LD = KC + 1;  // padded LDS row
 };
-
-// ---------------------------------------------------------------------------
-// Blocked left-looking Cholesky, one workgroup (4 waves) per subset.
-//
-// For every column block J (TB columns) and every chunk of CHUNK rows at or
-// below the diagonal block, the chunk of M = Sigma + lambda I is generated in
-// the MFMA accumulators, the update  - sum_{K<J} L_{rows,K} L_{J,K}^T  is
-// accumulated on MFMA from LDS-staged 128-byte row segments, and:
-//   - the diagonal block (wave 0 of the first chunk) goes to LDS in FP64,
-//     is factored there and inverted (FP64), log-pivots summed for log det;
-//   - every other row block is written back and multiplied on MFMA by the
-//     transposed inverse of the diagonal factor (the panel triangular solve).
-// Wave w owns rows [64w, 64w+64) of the chunk and all TB columns: 4 x 4
-// accumulator tiles of 16 x 16.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256, 1) void k_potrf(const SubsetDesc* __restrict__ desc,
-                                                  const int32_t* __restrict__ order,
-                                                  const ThetaDev* __restrict__ theta,
-                                                  const T* __restrict__ cx, const T* __restrict__ cy,
-                                                  T* __restrict__ Lbuf, double* __restrict__ Invbuf,
-                                                  double* __restrict__ logdet,
-                                                  int32_t* __restrict__ status) {
-  typedef typename Mfma<T>::acc_t acc_t;
-  typedef typename Vec16<T>::type vec_t;
-  constexpr int KC = Tile<T>::KC;
-  constexpr int LD = Tile<T>::LD;
-  constexpr int VW = Vec16<T>::W;
-  constexpr int STAGE_BYTES = (CHUNK + TB) * LD * (int)sizeof(T);
-  constexpr int DG_BYTES = TB * (TB + 1) * 8;
-  constexpr int U_BYTES = STAGE_BYTES > DG_BYTES ? STAGE_BYTES : DG_BYTES;
-  __shared__ __attribute__((aligned(16))) char smem_u[U_BYTES];
-  __shared__ double InvD[TB][TB + 1];
-  __shared__ double red[4][TB];
-
-  T* As = reinterpret_cast<T*>(smem_u);       // [CHUNK][LD]
-  T* Bs = As + CHUNK * LD;                     // [TB][LD]
-  double(*Dg)[TB + 1] = reinterpret_cast<double(*)[TB + 1]>(smem_u);
-
-  const int sidx = order[blockIdx.x];
-  const SubsetDesc D = desc[sidx];
-  const int n = D.n, npad = D.npad, nb = npad / TB;
-  T* __restrict__ L = Lbuf + D.offL;
-  double* __restrict__ Inv = Invbuf + D.offInv;
-  const T* __restrict__ X = cx + D.offT;
-  const T* __restrict__ Y = cy + D.offT;
-  const int cov = theta->cov;
-  const T ir = (T)theta->inv_range;
-  const T lam = (T)theta->lambda;
-
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int lr = l & 15, lk = l >> 4;
-  // staging map: thread -> (row within 32-row group, 16-byte column slot)
-  const int srow = tid >> 3, scol = (tid & 7) * VW;
-
-  double ld_acc = 0.0;
-  int bad = 0;
-
-  for (int J = 0; J < nb; ++J) {
-    const int c0 = J * TB;
-    for (int r0 = c0; r0 < npad; r0 += CHUNK) {
-      __syncthreads();  // previous chunk's writes visible, LDS free
-      const int wr0 = r0 + 64 * w;
-      const bool wact = wr0 < npad;
-      acc_t acc[4][4];
-
-      // ---- covariance tile: M[row][col] for the wave's 64 x TB block
-      if (wact) {
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-          const int col = c0 + 16 * bj + lr;
-          const T xc = col < n ? X[col] : (T)0, yc = col < n ? Y[col] : (T)0;
-#pragma unroll
-          for (int bi = 0; bi < 4; ++bi) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = wr0 + 16 * bi + Mfma<T>::crow(lk, v);
-              T val;
-              if (row < n && col < n) {
-                const T xr = X[row], yr = Y[row];
-                val = corr(cov, dist(xr - xc, yr - yc), ir) + (row == col ? lam : (T)0);
-              } else {
-                val = row == col ? (T)1 : (T)0;
-              }
-              acc[bi][bj][v] = val;
-            }
-          }
-        }
-      }
-
-      // ---- update: acc -= L[rows, 0:c0] * L[c0:c0+TB, 0:c0]^T
-      vec_t pa[8], pb[2];
-      auto prefetch = [&](int k0) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int row = r0 + 32 * s + srow;
-          if (row < npad)
-            pa[s] = *reinterpret_cast<const vec_t*>(L + packed_rowoff(row) + k0 + scol);
-          else
-            pa[s] = vec_t{};
-        }
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int row = c0 + 32 * s + srow;
-          pb[s] = *reinterpret_cast<const vec_t*>(L + packed_rowoff(row) + k0 + scol);
-        }
-      };
-      if (c0 > 0) prefetch(0);
-      for (int k0 = 0; k0 < c0; k0 += KC) {
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const T* p = reinterpret_cast<const T*>(&pa[s]);
-#pragma unroll
-          for (int e = 0; e < VW; ++e) As[(32 * s + srow) * LD + scol + e] = -p[e];
-        }
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const T* p = reinterpret_cast<const T*>(&pb[s]);
-#pragma unroll
-          for (int e = 0; e < VW; ++e) Bs[(32 * s + srow) * LD + scol + e] = p[e];
-        }
-        __syncthreads();
-        if (k0 + KC < c0) prefetch(k0 + KC);
-        if (wact) {
-#pragma unroll
-          for (int kk = 0; kk < KC / 4; ++kk) {
-            T a[4], b[4];
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi) a[bi] = As[(64 * w + 16 * bi + lr) * LD + 4 * kk + lk];
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) b[bj] = Bs[(16 * bj + lr) * LD + 4 * kk + lk];
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-              for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::mma(a[bi], b[bj], acc[bi][bj]);
-          }
-        }
-      }
-
-      // ---- diagonal block: FP64 factor + inverse in LDS
-      if (r0 == c0) {
-        __syncthreads();
-        if (w == 0) {
-#pragma unroll
-          for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) Dg[16 * bi + Mfma<T>::crow(lk, v)][16 * bj + lr] = (double)acc[bi][bj][v];
-        }
-        __syncthreads();
-        for (int j = 0; j < TB; ++j) {
-          if (tid == 0) {
-            double d = Dg[j][j];
-            if (!(d > 0.0) || !(d < 1e300)) {
-              if (!bad) bad = c0 + j + 1;
-              d = 1.0;
-            }
-            const double s = sqrt(d);
-            Dg[j][j] = s;
-            if (c0 + j < n) ld_acc += 2.0 * log(s);
-          }
-          __syncthreads();
-          const double piv = Dg[j][j];
-          if (tid > j && tid < TB) Dg[tid][j] /= piv;
-          __syncthreads();
-          const int m = TB - 1 - j;
-          for (int e = tid; e < m * m; e += 256) {
-            const int i = j + 1 + e / m, k = j + 1 + e % m;
-            if (k <= i) Dg[i][k] -= Dg[i][j] * Dg[k][j];
-          }
-          __syncthreads();
-        }
-        // inverse of the lower-triangular factor, row by row:
-        // Inv[i][c] = (delta_ic - sum_{c<=k<i} Dg[i][k] Inv[k][c]) / Dg[i][i]
-        {
-          const int c = tid & 63, q = tid >> 6;
-          for (int i = 0; i < TB; ++i) {
-            double s = 0.0;
-            for (int k = c + q; k < i; k += 4) s += Dg[i][k] * InvD[k][c];
-            red[q][c] = s;
-            __syncthreads();
-            if (q == 0) {
-              double v = 0.0;
-              if (c <= i) {
-                const double t = (c == i ? 1.0 : 0.0) - (red[0][c] + red[1][c] + red[2][c] + red[3][c]);
-                v = t / Dg[i][i];
-              }
-              InvD[i][c] = v;
-            }
-            __syncthreads();
-          }
-        }
-        // write L_JJ (T) and Inv_J (FP64)
-        for (int e = tid; e < TB * TB; e += 256) {
-          const int i = e / TB, j = e % TB;
-          L[packed_rowoff(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
-          Inv[(int64_t)J * TB * TB + e] = InvD[i][j];
-        }
-      }
-
-      // ---- panel triangular solve for the rows below the diagonal block:
-      //      L[rows, J] = Aupd[rows, J] * Inv_J^T
-      const bool offdiag = wact && !(r0 == c0 && w == 0);
-      if (offdiag) {
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = wr0 + 16 * bi + Mfma<T>::crow(lk, v);
-              L[packed_rowoff(row) + c0 + 16 * bj + lr] = acc[bi][bj][v];
-            }
-      }
-      const bool any_below = (r0 != c0) || (r0 + 64 < npad);
-      if (any_below) {
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = acc_t{};
-        for (int k0 = 0; k0 < TB; k0 += KC) {
-          __syncthreads();  // written rows visible; LDS free
-#pragma unroll
-          for (int s = 0; s < 8; ++s) {
-            const int row = r0 + 32 * s + srow;
-            vec_t v = vec_t{};
-            if (row < npad) v = *reinterpret_cast<const vec_t*>(L + packed_rowoff(row) + c0 + k0 + scol);
-            const T* p = reinterpret_cast<const T*>(&v);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) As[(32 * s + srow) * LD + scol + e] = p[e];
-          }
-          __syncthreads();
-          if (offdiag) {
-#pragma unroll
-            for (int kk = 0; kk < KC / 4; ++kk) {
-              T a[4], b[4];
-#pragma unroll
-              for (int bi = 0; bi < 4; ++bi) a[bi] = As[(64 * w + 16 * bi + lr) * LD + 4 * kk + lk];
-#pragma unroll
-              for (int bj = 0; bj < 4; ++bj) b[bj] = (T)InvD[16 * bj + lr][k0 + 4 * kk + lk];
-#pragma unroll
-              for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::mma(a[bi], b[bj], acc[bi][bj]);
-            }
-          }
-        }
-        __syncthreads();  // all staging reads done before overwriting
-        if (offdiag) {
-#pragma unroll
-          for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int row = wr0 + 16 * bi + Mfma<T>::crow(lk, v);
-                L[packed_rowoff(row) + c0 + 16 * bj + lr] = acc[bi][bj][v];
-              }
-        }
-      }
-    }
-  }
-  if (tid == 0) {
-    logdet[sidx] = ld_acc;
-    status[sidx] = bad;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Forward substitution L z = b, one workgroup per subset, FP64 accumulation.
@@ -616,25 +344,6 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
 }
 
 // ------------------------------------------------------------- launchers --
-template <typename T>
-static hipError_t potrf_launch(const Launch& Lc, const int32_t* order, int n_items, const T* cx,
-                               const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status) {
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_potrf<T>, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, order, Lc.theta, cx,
-                     cy, Lbuf, Inv, logdet, status);
-  return hipGetLastError();
-}
-hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, const float* cx,
-                            const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status) {
-  return potrf_launch<float>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
-}
-hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
-                            const double* cy, double* Lbuf, double* Inv, double* logdet,
-                            int32_t* status) {
-  return potrf_launch<double>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
-}
-
 template <typename T>
 static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items, const T* Lbuf,
                              const double* Inv, const double* rt, const double* rp, double* z,

@@ -1,0 +1,477 @@
+// Batched blocked Cholesky of the subset matrices M_i = Sigma_i(theta) +
+// lambda I (the (Sigma + lambda I)^{-1} of eq. (3), arXiv:1912.13132), one
+// workgroup of 4 waves per subset, two workgroups per compute unit.
+//
+// Left-looking over column panels of PB columns (PB = 128 for FP32, 64 for
+// FP64).  For every panel J and every chunk of 256 rows at or below the
+// diagonal, each wave keeps the TRANSPOSED chunk C^T (PB x 64) in MFMA
+// accumulators:
+//   1. C^T is initialised with the covariance (Sec. 3, exponential or
+//      Matern-3/2) of the chunk rows and panel columns, plus lambda on the
+//      diagonal (by index), generated from the subset's centred coordinates;
+//   2. C^T -= L_J L_R^T over all previous columns, on MFMA from 64-byte row
+//      segments staged through LDS (conflict-free 16-byte operand reads);
+//   3. the diagonal 64 x 64 blocks of the panel are factored in FP64 in LDS
+//      (right-looking, one barrier per column), inverted in FP64 into the
+//      free upper half of the same array, and the inverse is kept in LDS;
+//   4. the panel triangular solve X^T = L_JJ^{-1} C^T runs on MFMA with the
+//      accumulators themselves as the B operand (the contraction index is
+//      permuted to follow the accumulator layout), block row by block row
+//      from the bottom, in place: no transpose through memory;
+//   5. for FP32 panels the second 64-column half is first updated with the
+//      first half's solved columns (again from the accumulators), then
+//      factored and solved the same way;
+//   6. the finished rows are written to the packed tile-row factor.
+// The inverses of the diagonal blocks are also written (FP64) for the
+// triangular solves, and 2 sum log L_jj (FP64) for log det.
+#include <type_traits>
+
+#include "pcv_device.h"
+
+namespace pcv {
+namespace potrf {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Cfg;
+template <>
+struct Cfg<float> {
+  typedef f32x4 acc_t;
+  static constexpr int PB = 128;  // panel width
+  static constexpr int KC = 16;   // staged k per step (64 bytes of a row)
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element v of lane group g sits in row crow(g, v) of a 16x16 tile
+  static __device__ __forceinline__ int crow(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Cfg<double> {
+  typedef f64x4 acc_t;
+  static constexpr int PB = 64;
+  static constexpr int KC = 8;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int crow(int g, int v) { return 4 * v + g; }
+};
+
+__device__ __forceinline__ float corr_t(int cov, float d, float ir) {
+  const float t = d * ir;
+  const float e = expf(-t);
+  return cov == 1 ? (1.0f + t) * e : e;
+}
+__device__ __forceinline__ double corr_t(int cov, double d, double ir) {
+  const double t = d * ir;
+  const double e = exp(-t);
+  return cov == 1 ? (1.0 + t) * e : e;
+}
+
+// The four accumulator-row entries crow(g, 0..3) of a 16-wide LDS row segment.
+__device__ __forceinline__ void load_crow4(const float* row, int g, float (&a)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(row + 4 * g);
+  a[0] = v.x;
+  a[1] = v.y;
+  a[2] = v.z;
+  a[3] = v.w;
+}
+__device__ __forceinline__ void load_crow4(const double* row, int g, double (&a)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) a[v] = row[4 * v + g];
+}
+
+constexpr int RCH = 256;  // chunk rows (4 waves x 64)
+constexpr int LDD = 65;   // FP64 diagonal array row stride (doubles)
+
+template <typename T>
+struct Smem {
+  static constexpr int PB = Cfg<T>::PB;
+  static constexpr int KC = Cfg<T>::KC;
+  static constexpr int VW = 16 / sizeof(T);   // elements per 16-byte vector
+  static constexpr int LDK = KC + VW;         // staged row stride (80 bytes)
+  static constexpr int LDI = 64 + VW;         // inverse row stride
+  static constexpr int NSUB = PB / 64;
+  static constexpr int STAGE = (PB + RCH) * LDK * (int)sizeof(T);
+  static constexpr int L21 = 64 * LDI * (int)sizeof(T);
+  static constexpr int DG = 64 * LDD * 8;
+  static constexpr int U0 = STAGE > DG ? STAGE : DG;
+  static constexpr int U = U0 > L21 ? U0 : L21;
+};
+
+// In-register triangular solve on one 64-column sub-panel (accumulator block
+// rows B0..B0+3):  X^T = Inv * C^T, Inv lower triangular (LDS, row stride
+// LDI).  Output block row bo needs input block rows bk <= bo, so block rows
+// are produced from the bottom up and written in place.
+template <typename T, int B0, int NBI>
+__device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][4], const T* Inv, int lr,
+                                          int g) {
+  typedef typename Cfg<T>::acc_t acc_t;
+  constexpr int LDI = Smem<T>::LDI;
+#pragma unroll
+  for (int bo = 3; bo >= 0; --bo) {
+    acc_t tmp[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) tmp[bj] = acc_t{};
+#pragma unroll
+    for (int bk = 0; bk <= bo; ++bk) {
+      T a[4];
+      load_crow4(Inv + (16 * bo + lr) * LDI + 16 * bk, g, a);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) tmp[bj] = Cfg<T>::mma(a[v], acc[B0 + bk][bj][v], tmp[bj]);
+    }
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[B0 + bo][bj] = tmp[bj];
+  }
+}
+
+// FP64 factorisation of the 64 x 64 block in Dg (lower part), in place,
+// followed by the inverse of the factor, stored transposed in the free upper
+// part: Inv[i][c] (i >= c) lives at Dg[c][i + 1].  Adds 2 sum log L_jj over
+// rows < nreal to *ld and records the first failing pivot (1-based global
+// row) in *bad.  All 256 threads take part.
+__device__ void diag_factor_invert(double (*Dg)[LDD], double* piv, int nreal, int grow0, double& ld,
+                                   int& bad) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < 64; ++j) {
+    double p = Dg[j][j];
+    const bool ok = p > 0.0 && p < 1e300;
+    if (!ok) p = 1.0;
+    if (tid == 0) {
+      if (!ok && !bad) bad = grow0 + j + 1;
+      piv[j] = sqrt(p);
+      if (j < nreal) ld += log(p);
+    }
+    const int m = 63 - j;
+    const double ip = 1.0 / p;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) Dg[i][k] -= Dg[i][j] * Dg[k][j] * ip;
+    }
+    __syncthreads();
+  }
+  // scale columns: L_ij = A_ij / sqrt(p_j), L_jj = sqrt(p_j)
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (j < i) Dg[i][j] /= piv[j];
+    else if (j == i) Dg[i][i] = piv[i];
+  }
+  __syncthreads();
+  // inverse, row by row: Inv[i][c] = (delta_ic - sum_{c<=k<i} L_ik Inv[k][c]) / L_ii
+  __shared__ double red[4][64];
+  const int c = tid & 63, q = tid >> 6;
+  for (int i = 0; i < 64; ++i) {
+    double s = 0.0;
+    for (int k = c + q; k < i; k += 4) s += Dg[i][k] * Dg[c][k + 1];
+    red[q][c] = s;
+    __syncthreads();
+    if (q == 0 && c <= i) {
+      const double t = (c == i ? 1.0 : 0.0) - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
+      Dg[c][i + 1] = t / Dg[i][i];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
+                                                  const int32_t* __restrict__ order,
+                                                  const ThetaDev* __restrict__ theta,
+                                                  const T* __restrict__ cx, const T* __restrict__ cy,
+                                                  T* __restrict__ Lbuf, double* __restrict__ Invbuf,
+                                                  double* __restrict__ logdet,
+                                                  int32_t* __restrict__ status) {
+  typedef typename Cfg<T>::acc_t acc_t;
+  typedef Smem<T> SM;
+  constexpr int PB = SM::PB, KC = SM::KC, VW = SM::VW, LDK = SM::LDK, LDI = SM::LDI;
+  constexpr int NBI = PB / 16;
+  constexpr int NVEC = (PB + RCH) * (KC / VW);    // 16-byte vectors per stage
+  constexpr int VPT = NVEC / 256;                 // per thread
+  constexpr int VPR = KC / VW;                    // vectors per row (4)
+  typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
+
+  __shared__ __attribute__((aligned(16))) char smem_u[SM::U];
+  __shared__ __attribute__((aligned(16))) T InvS[SM::NSUB][64 * LDI];
+  __shared__ double piv[64];
+
+  T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
+  T* Rs = Ps + PB * LDK;                    // [RCH][LDK] chunk rows
+  T* L21s = reinterpret_cast<T*>(smem_u);  // [64][LDI]  -L21 (second half update)
+  double(*Dg)[LDD] = reinterpret_cast<double(*)[LDD]>(smem_u);
+
+  const int sidx = order[blockIdx.x];
+  const SubsetDesc D = desc[sidx];
+  const int n = D.n, npad = D.npad;
+  T* __restrict__ L = Lbuf + D.offL;
+  double* __restrict__ Inv = Invbuf + D.offInv;
+  const T* __restrict__ X = cx + D.offT;
+  const T* __restrict__ Y = cy + D.offT;
+  const int cov = theta->cov;
+  const T ir = (T)theta->inv_range;
+  const T lam = (T)theta->lambda;
+
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, g = l >> 4;
+
+  double ld = 0.0;
+  int bad = 0;
+
+  for (int c0 = 0; c0 < npad; c0 += PB) {
+    const bool two = (SM::NSUB == 2) && (c0 + 128 <= npad);
+    for (int r0 = c0; r0 < npad; r0 += RCH) {
+      const bool first = (r0 == c0);
+      const int wr0 = r0 + 64 * w;
+      const bool wact = wr0 < npad;
+      acc_t acc[NBI][4];
+      __syncthreads();  // previous chunk finished with LDS and global writes
+
+      // ---- 1. covariance: acc[bi][bj][v] = M[wr0 + 16 bj + lr][c0 + 16 bi + crow(g, v)]
+      //      (branch-free: indices clamped into the subset, padding selected afterwards)
+      if (wact) {
+        T xr[4], yr[4];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+          const int row = min(wr0 + 16 * bj + lr, n - 1);
+          xr[bj] = X[row];
+          yr[bj] = Y[row];
+        }
+#pragma unroll
+        for (int bi = 0; bi < NBI; ++bi) {
+          T tv[4][4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = c0 + 16 * bi + Cfg<T>::crow(g, v);
+            const int colc = min(col, n - 1);
+            const T xc = X[colc], yc = Y[colc];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+              const int row = wr0 + 16 * bj + lr;
+              const T dx = xr[bj] - xc, dy = yr[bj] - yc;
+              const T cv = corr_t(cov, sqrt(dx * dx + dy * dy), ir);
+              const bool diag = row == col;
+              const bool real = (row < n) & (col < n);
+              tv[bj][v] = real ? cv + (diag ? lam : (T)0) : (diag ? (T)1 : (T)0);
+            }
+          }
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = acc_t{tv[bj][0], tv[bj][1], tv[bj][2], tv[bj][3]};
+          // keep the scheduler from hoisting every column's loads and exponentials
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+
+      // ---- 2. update: C^T -= L[c0:c0+PB, 0:c0] L[rows, 0:c0]^T
+      if (c0 > 0) {
+        // staging map: vector vi = tid + 256 s -> (row vi / VPR, 16-byte column slot vi % VPR);
+        // rows [0, PB) are panel rows, the rest chunk rows
+        int goff[VPT];
+        bool gok[VPT];
+#pragma unroll
+        for (int s = 0; s < VPT; ++s) {
+          const int vi = tid + 256 * s;
+          const int row = vi / VPR, cv = vi % VPR;
+          const int grow = row < PB ? c0 + row : r0 + (row - PB);
+          gok[s] = grow < npad;
+          goff[s] = packed_rowoff32(gok[s] ? grow : 0) + cv * VW;
+        }
+        vec_t st[VPT];
+#pragma unroll
+        for (int s = 0; s < VPT; ++s) {
+          const vec_t v = *reinterpret_cast<const vec_t*>(L + goff[s]);
+          st[s] = gok[s] ? v : vec_t{};
+        }
+        for (int k0 = 0; k0 < c0; k0 += KC) {
+          __syncthreads();
+#pragma unroll
+          for (int s = 0; s < VPT; ++s) {
+            const int vi = tid + 256 * s;
+            const int row = vi / VPR, cv = vi % VPR;
+            vec_t v = st[s];
+            if (row < PB) {
+              T* p = reinterpret_cast<T*>(&v);
+#pragma unroll
+              for (int e = 0; e < VW; ++e) p[e] = -p[e];
+            }
+            *reinterpret_cast<vec_t*>(Ps + row * LDK + cv * VW) = v;  // Rs follows Ps
+          }
+          __syncthreads();
+          if (k0 + KC < c0) {
+#pragma unroll
+            for (int s = 0; s < VPT; ++s) {
+              const vec_t v = *reinterpret_cast<const vec_t*>(L + goff[s] + k0 + KC);
+              st[s] = gok[s] ? v : vec_t{};
+            }
+          }
+          if (wact) {
+            // lane group g takes k = g * VW + s for the VW MFMA steps s
+            static_assert(KC / 4 == VW, "one 16-byte LDS read per operand block");
+            vec_t rb[4];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+              rb[bj] = *reinterpret_cast<const vec_t*>(Rs + (64 * w + 16 * bj + lr) * LDK + g * VW);
+#pragma unroll
+            for (int h = 0; h < NBI; h += 2) {
+              vec_t pa[2];
+#pragma unroll
+              for (int b = 0; b < 2; ++b)
+                pa[b] = *reinterpret_cast<const vec_t*>(Ps + (16 * (h + b) + lr) * LDK + g * VW);
+#pragma unroll
+              for (int s = 0; s < VW; ++s)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                  for (int bj = 0; bj < 4; ++bj)
+                    acc[h + b][bj] = Cfg<T>::mma(reinterpret_cast<const T*>(&pa[b])[s],
+                                                 reinterpret_cast<const T*>(&rb[bj])[s], acc[h + b][bj]);
+            }
+          }
+        }
+      }
+
+      // ---- 3/4. first sub-panel: diagonal block (first chunk), then solve
+      if (first) {
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                Dg[16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[bi][bj][v];
+        }
+        __syncthreads();
+        diag_factor_invert(Dg, piv, n - c0, c0, ld, bad);
+        for (int e = tid; e < 64 * 64; e += 256) {
+          const int i = e >> 6, j = e & 63;
+          L[packed_rowoff32(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
+          const double iv = j <= i ? Dg[j][i + 1] : 0.0;
+          Inv[(int64_t)(c0 / 64) * 4096 + e] = iv;
+          InvS[0][i * LDI + j] = (T)iv;
+        }
+        __syncthreads();
+      }
+      const bool solve_rows = wact && !(first && w == 0);
+      if (solve_rows) trsm_regs<T, 0, NBI>(acc, InvS[0], lr, g);
+
+      if constexpr (SM::NSUB == 2) {
+        if (two) {
+          // ---- 5. second half: C2^T -= L21 X0^T, then factor / solve
+          __syncthreads();
+          if (first) {
+            if (w == 1) {
+#pragma unroll
+              for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                  for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * bj + lr, k = 16 * bi + Cfg<T>::crow(g, v);
+                    L21s[i * LDI + k] = -acc[bi][bj][v];
+                  }
+            }
+          } else {
+            for (int e = tid; e < 64 * 16; e += 256) {
+              const int i = e >> 4, k4 = (e & 15) * 4;
+              const float4 v = *reinterpret_cast<const float4*>(
+                  reinterpret_cast<const float*>(L) + packed_rowoff32(c0 + 64 + i) + c0 + k4);
+              float* q = reinterpret_cast<float*>(L21s) + i * LDI + k4;
+              q[0] = -v.x;
+              q[1] = -v.y;
+              q[2] = -v.z;
+              q[3] = -v.w;
+            }
+          }
+          __syncthreads();
+          const bool upd = wact && !(first && w == 0);
+          if (upd) {
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+              for (int bk = 0; bk < 4; ++bk) {
+                T a[4];
+                load_crow4(L21s + (16 * bi + lr) * LDI + 16 * bk, g, a);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                  for (int bj = 0; bj < 4; ++bj)
+                    acc[4 + bi][bj] = Cfg<T>::mma(a[v], acc[bk][bj][v], acc[4 + bi][bj]);
+              }
+            }
+          }
+          if (first) {
+            __syncthreads();
+            if (w == 1) {
+#pragma unroll
+              for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                  for (int v = 0; v < 4; ++v)
+                    Dg[16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[4 + bi][bj][v];
+            }
+            __syncthreads();
+            diag_factor_invert(Dg, piv, n - c0 - 64, c0 + 64, ld, bad);
+            for (int e = tid; e < 64 * 64; e += 256) {
+              const int i = e >> 6, j = e & 63;
+              L[packed_rowoff32(c0 + 64 + i) + c0 + 64 + j] = j <= i ? (T)Dg[i][j] : (T)0;
+              const double iv = j <= i ? Dg[j][i + 1] : 0.0;
+              Inv[(int64_t)(c0 / 64 + 1) * 4096 + e] = iv;
+              InvS[1][i * LDI + j] = (T)iv;
+            }
+            __syncthreads();
+          }
+          const bool solve2 = wact && !(first && w <= 1);
+          if (solve2) trsm_regs<T, 4, NBI>(acc, InvS[1], lr, g);
+        }
+      }
+
+      // ---- 6. store the finished rows
+      if (wact && !(first && w == 0)) {
+        const int nbs = (first && w == 1) ? 4 : (two ? NBI : 4);
+#pragma unroll
+        for (int bi = 0; bi < NBI; ++bi) {
+          if (bi < nbs) {
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+              const int row = wr0 + 16 * bj + lr;
+              T* dst = L + packed_rowoff32(row) + c0 + 16 * bi;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) dst[Cfg<T>::crow(g, v)] = acc[bi][bj][v];
+            }
+          }
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    logdet[sidx] = ld;
+    status[sidx] = bad;
+  }
+}
+
+}  // namespace potrf
+
+template <typename T>
+static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_items, const T* cx,
+                                const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(potrf::k_potrf<T>, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, order, Lc.theta,
+                     cx, cy, Lbuf, Inv, logdet, status);
+  return hipGetLastError();
+}
+hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, const float* cx,
+                            const float* cy, float* Lbuf, double* Inv, double* logdet,
+                            int32_t* status) {
+  return potrf2_launch<float>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
+}
+hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
+                            const double* cy, double* Lbuf, double* Inv, double* logdet,
+                            int32_t* status) {
+  return potrf2_launch<double>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
+}
+
+}  // namespace pcv
