@@ -38,7 +38,9 @@ struct pcv_problem {
   int2* d_row_items = nullptr;
   int2* d_val_items = nullptr;
   double *d_tx = nullptr, *d_ty = nullptr, *d_yT = nullptr;
-  float *d_tx32 = nullptr, *d_ty32 = nullptr;
+  // factorisation coordinates, padded to npad per subset with +inf (offP)
+  double *d_px64 = nullptr, *d_py64 = nullptr;
+  float *d_px32 = nullptr, *d_py32 = nullptr;
   double *d_vx = nullptr, *d_vy = nullptr, *d_yV = nullptr;
   double *d_z = nullptr, *d_x = nullptr, *d_alpha = nullptr, *d_r = nullptr, *d_rhs2 = nullptr;
   double *d_yhat = nullptr, *d_err = nullptr;

@@ -1,14 +1,17 @@
 // Batched blocked Cholesky of the subset matrices M_i = Sigma_i(theta) +
 // lambda I (the (Sigma + lambda I)^{-1} of eq. (3), arXiv:1912.13132), one
-// workgroup of 4 waves per subset, two workgroups per compute unit.
+// workgroup of 8 waves per subset, two workgroups per compute unit.
 //
 // Left-looking over column panels of PB columns (PB = 128 for FP32, 64 for
 // FP64).  For every panel J and every chunk of 256 rows at or below the
-// diagonal, each wave keeps the TRANSPOSED chunk C^T (PB x 64) in MFMA
+// diagonal, each wave keeps the TRANSPOSED chunk C^T (PB x 32) in MFMA
 // accumulators:
 //   1. C^T is initialised with the covariance (Sec. 3, exponential or
-//      Matern-3/2) of the chunk rows and panel columns, plus lambda on the
-//      diagonal (by index), generated from the subset's centred coordinates;
+//      Matern-3/2) of the chunk rows and panel columns, generated from the
+//      subset's centred coordinates (padded to npad with points at infinity,
+//      whose entries are 0, so padding rows form an identity block); lambda
+//      (and the padding's unit diagonal) is set by index when the diagonal
+//      block is moved to FP64;
 //   2. C^T -= L_J L_R^T over all previous columns, on MFMA from 64-byte row
 //      segments staged through LDS (conflict-free 16-byte operand reads);
 //   3. the diagonal 64 x 64 blocks of the panel are factored in FP64 in LDS
@@ -58,15 +61,20 @@ struct Cfg<double> {
   static __device__ __forceinline__ int crow(int g, int v) { return 4 * v + g; }
 };
 
+// Correlation of Sec. 3 (exponential) or Matern-3/2.  Padding points carry
+// infinite coordinates: their distance to anything is inf or NaN, and the
+// entry is then exactly 0.
 __device__ __forceinline__ float corr_t(int cov, float d, float ir) {
   const float t = d * ir;
   const float e = expf(-t);
-  return cov == 1 ? (1.0f + t) * e : e;
+  const float c = cov == 1 ? (1.0f + t) * e : e;
+  return d < INFINITY ? c : 0.0f;
 }
 __device__ __forceinline__ double corr_t(int cov, double d, double ir) {
   const double t = d * ir;
   const double e = exp(-t);
-  return cov == 1 ? (1.0 + t) * e : e;
+  const double c = cov == 1 ? (1.0 + t) * e : e;
+  return d < INFINITY ? c : 0.0;
 }
 
 // The four accumulator-row entries crow(g, 0..3) of a 16-wide LDS row segment.
@@ -82,7 +90,10 @@ __device__ __forceinline__ void load_crow4(const double* row, int g, double (&a)
   for (int v = 0; v < 4; ++v) a[v] = row[4 * v + g];
 }
 
-constexpr int RCH = 256;  // chunk rows (4 waves x 64)
+constexpr int NT = 512;   // threads per workgroup (8 waves)
+constexpr int WR = 32;    // chunk rows per wave
+constexpr int NBJ = WR / 16;
+constexpr int RCH = NT / 64 * WR;  // chunk rows (256)
 constexpr int LDD = 65;   // FP64 diagonal array row stride (doubles)
 
 template <typename T>
@@ -104,16 +115,16 @@ struct Smem {
 // rows B0..B0+3):  X^T = Inv * C^T, Inv lower triangular (LDS, row stride
 // LDI).  Output block row bo needs input block rows bk <= bo, so block rows
 // are produced from the bottom up and written in place.
-template <typename T, int B0, int NBI>
-__device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][4], const T* Inv, int lr,
+template <typename T, int B0, int NBI, int NB>
+__device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB], const T* Inv, int lr,
                                           int g) {
   typedef typename Cfg<T>::acc_t acc_t;
   constexpr int LDI = Smem<T>::LDI;
 #pragma unroll
   for (int bo = 3; bo >= 0; --bo) {
-    acc_t tmp[4];
+    acc_t tmp[NB];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) tmp[bj] = acc_t{};
+    for (int bj = 0; bj < NB; ++bj) tmp[bj] = acc_t{};
 #pragma unroll
     for (int bk = 0; bk <= bo; ++bk) {
       T a[4];
@@ -121,10 +132,10 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][4],
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) tmp[bj] = Cfg<T>::mma(a[v], acc[B0 + bk][bj][v], tmp[bj]);
+        for (int bj = 0; bj < NB; ++bj) tmp[bj] = Cfg<T>::mma(a[v], acc[B0 + bk][bj][v], tmp[bj]);
     }
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[B0 + bo][bj] = tmp[bj];
+    for (int bj = 0; bj < NB; ++bj) acc[B0 + bo][bj] = tmp[bj];
   }
 }
 
@@ -132,7 +143,7 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][4],
 // followed by the inverse of the factor, stored transposed in the free upper
 // part: Inv[i][c] (i >= c) lives at Dg[c][i + 1].  Adds 2 sum log L_jj over
 // rows < nreal to *ld and records the first failing pivot (1-based global
-// row) in *bad.  All 256 threads take part.
+// row) in *bad.  All NT threads take part.
 __device__ void diag_factor_invert(double (*Dg)[LDD], double* piv, int nreal, int grow0, double& ld,
                                    int& bad) {
   const int tid = threadIdx.x;
@@ -147,29 +158,33 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double* piv, int nreal, in
     }
     const int m = 63 - j;
     const double ip = 1.0 / p;
-    for (int e = tid; e < m * m; e += 256) {
+    for (int e = tid; e < m * m; e += NT) {
       const int i = j + 1 + e / m, k = j + 1 + e % m;
       if (k <= i) Dg[i][k] -= Dg[i][j] * Dg[k][j] * ip;
     }
     __syncthreads();
   }
   // scale columns: L_ij = A_ij / sqrt(p_j), L_jj = sqrt(p_j)
-  for (int e = tid; e < 64 * 64; e += 256) {
+  for (int e = tid; e < 64 * 64; e += NT) {
     const int i = e >> 6, j = e & 63;
     if (j < i) Dg[i][j] /= piv[j];
     else if (j == i) Dg[i][i] = piv[i];
   }
   __syncthreads();
   // inverse, row by row: Inv[i][c] = (delta_ic - sum_{c<=k<i} L_ik Inv[k][c]) / L_ii
-  __shared__ double red[4][64];
+  constexpr int NQ = NT / 64;
+  __shared__ double red[NQ][64];
   const int c = tid & 63, q = tid >> 6;
   for (int i = 0; i < 64; ++i) {
     double s = 0.0;
-    for (int k = c + q; k < i; k += 4) s += Dg[i][k] * Dg[c][k + 1];
+    for (int k = c + q; k < i; k += NQ) s += Dg[i][k] * Dg[c][k + 1];
     red[q][c] = s;
     __syncthreads();
     if (q == 0 && c <= i) {
-      const double t = (c == i ? 1.0 : 0.0) - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
+      double r = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < NQ; ++qq) r += red[qq][c];
+      const double t = (c == i ? 1.0 : 0.0) - r;
       Dg[c][i + 1] = t / Dg[i][i];
     }
     __syncthreads();
@@ -177,25 +192,26 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double* piv, int nreal, in
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
-                                                  const int32_t* __restrict__ order,
-                                                  const ThetaDev* __restrict__ theta,
-                                                  const T* __restrict__ cx, const T* __restrict__ cy,
-                                                  T* __restrict__ Lbuf, double* __restrict__ Invbuf,
-                                                  double* __restrict__ logdet,
-                                                  int32_t* __restrict__ status) {
+__global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ desc,
+                                                 const int32_t* __restrict__ order,
+                                                 const ThetaDev* __restrict__ theta,
+                                                 const T* __restrict__ cx, const T* __restrict__ cy,
+                                                 T* __restrict__ Lbuf, double* __restrict__ Invbuf,
+                                                 double* __restrict__ logdet,
+                                                 int32_t* __restrict__ status) {
   typedef typename Cfg<T>::acc_t acc_t;
   typedef Smem<T> SM;
   constexpr int PB = SM::PB, KC = SM::KC, VW = SM::VW, LDK = SM::LDK, LDI = SM::LDI;
-  constexpr int NBI = PB / 16;
+  constexpr int NBI = PB / 16;                    // accumulator block rows (panel columns)
   constexpr int NVEC = (PB + RCH) * (KC / VW);    // 16-byte vectors per stage
-  constexpr int VPT = NVEC / 256;                 // per thread
+  constexpr int VPT = (NVEC + NT - 1) / NT;       // per thread
   constexpr int VPR = KC / VW;                    // vectors per row (4)
   typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
 
   __shared__ __attribute__((aligned(16))) char smem_u[SM::U];
   __shared__ __attribute__((aligned(16))) T InvS[SM::NSUB][64 * LDI];
   __shared__ double piv[64];
+  __shared__ T colx[PB], coly[PB];  // the current panel's column coordinates
 
   T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
   T* Rs = Ps + PB * LDK;                    // [RCH][LDK] chunk rows
@@ -207,11 +223,11 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
   const int n = D.n, npad = D.npad;
   T* __restrict__ L = Lbuf + D.offL;
   double* __restrict__ Inv = Invbuf + D.offInv;
-  const T* __restrict__ X = cx + D.offT;
-  const T* __restrict__ Y = cy + D.offT;
+  const T* __restrict__ X = cx + D.offP;  // padded coordinates (npad entries)
+  const T* __restrict__ Y = cy + D.offP;
   const int cov = theta->cov;
   const T ir = (T)theta->inv_range;
-  const T lam = (T)theta->lambda;
+  const double lam64 = theta->lambda;
 
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int lr = l & 15, g = l >> 4;
@@ -221,60 +237,64 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
 
   for (int c0 = 0; c0 < npad; c0 += PB) {
     const bool two = (SM::NSUB == 2) && (c0 + 128 <= npad);
+    __syncthreads();  // previous panel done with colx / coly
+    if (tid < PB) {
+      const int col = min(c0 + tid, npad - 1);
+      colx[tid] = X[col];
+      coly[tid] = Y[col];
+    }
     for (int r0 = c0; r0 < npad; r0 += RCH) {
       const bool first = (r0 == c0);
-      const int wr0 = r0 + 64 * w;
+      const int wr0 = r0 + WR * w;          // this wave's first row
       const bool wact = wr0 < npad;
-      acc_t acc[NBI][4];
+      // In the first chunk, waves 0,1 hold the diagonal block of the first
+      // 64 columns, waves 2,3 the second 64 rows of the panel.
+      const int wpos = first ? w : 8;     // 8 = an ordinary row block
+      acc_t acc[NBI][NBJ];
       __syncthreads();  // previous chunk finished with LDS and global writes
 
-      // ---- 1. covariance: acc[bi][bj][v] = M[wr0 + 16 bj + lr][c0 + 16 bi + crow(g, v)]
-      //      (branch-free: indices clamped into the subset, padding selected afterwards)
+      // ---- 1. covariance: acc[bi][bj][v] = c(|s_row - s_col|) for row = wr0 + 16 bj + lr,
+      //      col = c0 + 16 bi + crow(g, v).  Padding points are at infinity, so
+      //      their entries are exactly 0; the nugget and the padding's unit
+      //      diagonal are set on the diagonal blocks in FP64 (step 3).
       if (wact) {
-        T xr[4], yr[4];
+        T xr[NBJ], yr[NBJ];
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-          const int row = min(wr0 + 16 * bj + lr, n - 1);
+        for (int bj = 0; bj < NBJ; ++bj) {
+          const int row = wr0 + 16 * bj + lr;
           xr[bj] = X[row];
           yr[bj] = Y[row];
         }
 #pragma unroll
         for (int bi = 0; bi < NBI; ++bi) {
-          T tv[4][4];
+          T tv[NBJ][4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int col = c0 + 16 * bi + Cfg<T>::crow(g, v);
-            const int colc = min(col, n - 1);
-            const T xc = X[colc], yc = Y[colc];
+            const int cl = 16 * bi + Cfg<T>::crow(g, v);
+            const T xc = colx[cl], yc = coly[cl];
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
-              const int row = wr0 + 16 * bj + lr;
+            for (int bj = 0; bj < NBJ; ++bj) {
               const T dx = xr[bj] - xc, dy = yr[bj] - yc;
-              const T cv = corr_t(cov, sqrt(dx * dx + dy * dy), ir);
-              const bool diag = row == col;
-              const bool real = (row < n) & (col < n);
-              tv[bj][v] = real ? cv + (diag ? lam : (T)0) : (diag ? (T)1 : (T)0);
+              tv[bj][v] = corr_t(cov, sqrt(dx * dx + dy * dy), ir);
             }
           }
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = acc_t{tv[bj][0], tv[bj][1], tv[bj][2], tv[bj][3]};
-          // keep the scheduler from hoisting every column's loads and exponentials
-          __builtin_amdgcn_sched_barrier(0);
+          for (int bj = 0; bj < NBJ; ++bj) acc[bi][bj] = acc_t{tv[bj][0], tv[bj][1], tv[bj][2], tv[bj][3]};
         }
       }
 
       // ---- 2. update: C^T -= L[c0:c0+PB, 0:c0] L[rows, 0:c0]^T
       if (c0 > 0) {
-        // staging map: vector vi = tid + 256 s -> (row vi / VPR, 16-byte column slot vi % VPR);
+        // staging map: vector vi = tid + NT s -> (row vi / VPR, 16-byte column slot vi % VPR);
         // rows [0, PB) are panel rows, the rest chunk rows
         int goff[VPT];
         bool gok[VPT];
 #pragma unroll
         for (int s = 0; s < VPT; ++s) {
-          const int vi = tid + 256 * s;
+          const int vi = tid + NT * s;
           const int row = vi / VPR, cv = vi % VPR;
           const int grow = row < PB ? c0 + row : r0 + (row - PB);
-          gok[s] = grow < npad;
+          gok[s] = (vi < NVEC) & (grow < npad);
           goff[s] = packed_rowoff32(gok[s] ? grow : 0) + cv * VW;
         }
         vec_t st[VPT];
@@ -287,7 +307,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
           __syncthreads();
 #pragma unroll
           for (int s = 0; s < VPT; ++s) {
-            const int vi = tid + 256 * s;
+            const int vi = tid + NT * s;
             const int row = vi / VPR, cv = vi % VPR;
             vec_t v = st[s];
             if (row < PB) {
@@ -295,7 +315,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
 #pragma unroll
               for (int e = 0; e < VW; ++e) p[e] = -p[e];
             }
-            *reinterpret_cast<vec_t*>(Ps + row * LDK + cv * VW) = v;  // Rs follows Ps
+            if (vi < NVEC) *reinterpret_cast<vec_t*>(Ps + row * LDK + cv * VW) = v;  // Rs follows Ps
           }
           __syncthreads();
           if (k0 + KC < c0) {
@@ -308,22 +328,22 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
           if (wact) {
             // lane group g takes k = g * VW + s for the VW MFMA steps s
             static_assert(KC / 4 == VW, "one 16-byte LDS read per operand block");
-            vec_t rb[4];
+            vec_t rb[NBJ];
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
-              rb[bj] = *reinterpret_cast<const vec_t*>(Rs + (64 * w + 16 * bj + lr) * LDK + g * VW);
+            for (int bj = 0; bj < NBJ; ++bj)
+              rb[bj] = *reinterpret_cast<const vec_t*>(Rs + (WR * w + 16 * bj + lr) * LDK + g * VW);
 #pragma unroll
-            for (int h = 0; h < NBI; h += 2) {
-              vec_t pa[2];
+            for (int h = 0; h < NBI; h += 4) {
+              vec_t pa[4];
 #pragma unroll
-              for (int b = 0; b < 2; ++b)
+              for (int b = 0; b < 4; ++b)
                 pa[b] = *reinterpret_cast<const vec_t*>(Ps + (16 * (h + b) + lr) * LDK + g * VW);
 #pragma unroll
               for (int s = 0; s < VW; ++s)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < 4; ++b)
 #pragma unroll
-                  for (int bj = 0; bj < 4; ++bj)
+                  for (int bj = 0; bj < NBJ; ++bj)
                     acc[h + b][bj] = Cfg<T>::mma(reinterpret_cast<const T*>(&pa[b])[s],
                                                  reinterpret_cast<const T*>(&rb[bj])[s], acc[h + b][bj]);
             }
@@ -334,18 +354,20 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
       // ---- 3/4. first sub-panel: diagonal block (first chunk), then solve
       if (first) {
         __syncthreads();
-        if (w == 0) {
+        if (wpos < 2) {
 #pragma unroll
           for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < NBJ; ++bj)
 #pragma unroll
               for (int v = 0; v < 4; ++v)
-                Dg[16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[bi][bj][v];
+                Dg[WR * wpos + 16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[bi][bj][v];
         }
         __syncthreads();
+        if (tid < 64) Dg[tid][tid] = c0 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
+        __syncthreads();
         diag_factor_invert(Dg, piv, n - c0, c0, ld, bad);
-        for (int e = tid; e < 64 * 64; e += 256) {
+        for (int e = tid; e < 64 * 64; e += NT) {
           const int i = e >> 6, j = e & 63;
           L[packed_rowoff32(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
           const double iv = j <= i ? Dg[j][i + 1] : 0.0;
@@ -354,27 +376,26 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
         }
         __syncthreads();
       }
-      const bool solve_rows = wact && !(first && w == 0);
-      if (solve_rows) trsm_regs<T, 0, NBI>(acc, InvS[0], lr, g);
+      if (wact && wpos >= 2) trsm_regs<T, 0, NBI, NBJ>(acc, InvS[0], lr, g);
 
       if constexpr (SM::NSUB == 2) {
         if (two) {
           // ---- 5. second half: C2^T -= L21 X0^T, then factor / solve
           __syncthreads();
           if (first) {
-            if (w == 1) {
+            if (wpos == 2 || wpos == 3) {
 #pragma unroll
               for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < NBJ; ++bj)
 #pragma unroll
                   for (int v = 0; v < 4; ++v) {
-                    const int i = 16 * bj + lr, k = 16 * bi + Cfg<T>::crow(g, v);
+                    const int i = WR * (wpos - 2) + 16 * bj + lr, k = 16 * bi + Cfg<T>::crow(g, v);
                     L21s[i * LDI + k] = -acc[bi][bj][v];
                   }
             }
           } else {
-            for (int e = tid; e < 64 * 16; e += 256) {
+            for (int e = tid; e < 64 * 16; e += NT) {
               const int i = e >> 4, k4 = (e & 15) * 4;
               const float4 v = *reinterpret_cast<const float4*>(
                   reinterpret_cast<const float*>(L) + packed_rowoff32(c0 + 64 + i) + c0 + k4);
@@ -386,8 +407,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
             }
           }
           __syncthreads();
-          const bool upd = wact && !(first && w == 0);
-          if (upd) {
+          if (wact && wpos >= 2) {
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi) {
 #pragma unroll
@@ -397,25 +417,27 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
-                  for (int bj = 0; bj < 4; ++bj)
+                  for (int bj = 0; bj < NBJ; ++bj)
                     acc[4 + bi][bj] = Cfg<T>::mma(a[v], acc[bk][bj][v], acc[4 + bi][bj]);
               }
             }
           }
           if (first) {
             __syncthreads();
-            if (w == 1) {
+            if (wpos == 2 || wpos == 3) {
 #pragma unroll
               for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < NBJ; ++bj)
 #pragma unroll
                   for (int v = 0; v < 4; ++v)
-                    Dg[16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[4 + bi][bj][v];
+                    Dg[WR * (wpos - 2) + 16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[4 + bi][bj][v];
             }
             __syncthreads();
+            if (tid < 64) Dg[tid][tid] = c0 + 64 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
+            __syncthreads();
             diag_factor_invert(Dg, piv, n - c0 - 64, c0 + 64, ld, bad);
-            for (int e = tid; e < 64 * 64; e += 256) {
+            for (int e = tid; e < 64 * 64; e += NT) {
               const int i = e >> 6, j = e & 63;
               L[packed_rowoff32(c0 + 64 + i) + c0 + 64 + j] = j <= i ? (T)Dg[i][j] : (T)0;
               const double iv = j <= i ? Dg[j][i + 1] : 0.0;
@@ -424,23 +446,26 @@ __global__ __launch_bounds__(256, 2) void k_potrf(const SubsetDesc* __restrict__
             }
             __syncthreads();
           }
-          const bool solve2 = wact && !(first && w <= 1);
-          if (solve2) trsm_regs<T, 4, NBI>(acc, InvS[1], lr, g);
+          if (wact && wpos >= 4) trsm_regs<T, 4, NBI, NBJ>(acc, InvS[1], lr, g);
         }
       }
 
       // ---- 6. store the finished rows
-      if (wact && !(first && w == 0)) {
-        const int nbs = (first && w == 1) ? 4 : (two ? NBI : 4);
+      if (wact && wpos >= 2) {
+        const int nbs = (wpos < 4) ? 4 : (two ? NBI : 4);
 #pragma unroll
         for (int bi = 0; bi < NBI; ++bi) {
           if (bi < nbs) {
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
+            for (int bj = 0; bj < NBJ; ++bj) {
               const int row = wr0 + 16 * bj + lr;
               T* dst = L + packed_rowoff32(row) + c0 + 16 * bi;
+              if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<acc_t*>(dst + 4 * g) = acc[bi][bj];
+              } else {
 #pragma unroll
-              for (int v = 0; v < 4; ++v) dst[Cfg<T>::crow(g, v)] = acc[bi][bj][v];
+                for (int v = 0; v < 4; ++v) dst[Cfg<T>::crow(g, v)] = acc[bi][bj][v];
+              }
             }
           }
         }
@@ -459,7 +484,7 @@ template <typename T>
 static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_items, const T* cx,
                                 const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(potrf::k_potrf<T>, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, order, Lc.theta,
+  hipLaunchKernelGGL(potrf::k_potrf<T>, dim3(n_items), dim3(potrf::NT), 0, Lc.stream, Lc.desc, order, Lc.theta,
                      cx, cy, Lbuf, Inv, logdet, status);
   return hipGetLastError();
 }

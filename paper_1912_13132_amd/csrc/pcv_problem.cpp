@@ -223,7 +223,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
 
   // per-subset panels, centred on the subset's training centroid (FP64)
   std::vector<double> tx(offT), ty(offT), yT(offT), vx(offV), vy(offV), yV(offV);
-  std::vector<float> tx32(offT), ty32(offT);
+  std::vector<double> px64(offP, INFINITY), py64(offP, INFINITY);
+  std::vector<float> px32(offP, INFINITY), py32(offP, INFINITY);
   for (int32_t i = 0; i < S; ++i) {
     const SubsetDesc& d = p->desc[i];
     double cx = 0.0, cy = 0.0;
@@ -249,8 +250,10 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
       const int64_t g = tidx[j];
       tx[d.offT + a] = locs[2 * g] - cx;
       ty[d.offT + a] = locs[2 * g + 1] - cy;
-      tx32[d.offT + a] = (float)tx[d.offT + a];
-      ty32[d.offT + a] = (float)ty[d.offT + a];
+      px64[d.offP + a] = tx[d.offT + a];
+      py64[d.offP + a] = ty[d.offT + a];
+      px32[d.offP + a] = (float)tx[d.offT + a];
+      py32[d.offP + a] = (float)ty[d.offT + a];
       yT[d.offT + a] = y[g];
       y2 += y[g] * y[g];
     }
@@ -278,8 +281,10 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(upload(p, &p->d_tx, tx));
   TRY(upload(p, &p->d_ty, ty));
   TRY(upload(p, &p->d_yT, yT));
-  TRY(upload(p, &p->d_tx32, tx32));
-  TRY(upload(p, &p->d_ty32, ty32));
+  TRY(upload(p, &p->d_px32, px32));
+  TRY(upload(p, &p->d_py32, py32));
+  TRY(upload(p, &p->d_px64, px64));
+  TRY(upload(p, &p->d_py64, py64));
   TRY(upload(p, &p->d_vx, vx));
   TRY(upload(p, &p->d_vy, vy));
   TRY(upload(p, &p->d_yV, yV));
@@ -332,7 +337,7 @@ pcv_status factor_solve64(pcv_problem* p, const ThetaDev* d_theta, const int32_t
                           double* Lb, double* Invb, double* zb, double* alphab, double* logdetb,
                           int32_t* statusb) {
   Launch Lc{p->stream, p->d_desc, d_theta};
-  HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_tx, p->d_ty, Lb, Invb, logdetb, statusb));
+  HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_px64, p->d_py64, Lb, Invb, logdetb, statusb));
   HIPCHK(launch_trsv_fwd_f64(Lc, d_order, count, Lb, Invb, p->d_yT, nullptr, zb, nullptr));
   HIPCHK(launch_trsv_bwd_f64(Lc, d_order, count, Lb, Invb, zb, alphab, nullptr));
   return PCV_OK;
@@ -352,10 +357,10 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   const bool ev = p->events;
   if (ev) HIPCHK(hipEventRecord(p->ev[0], p->stream));
   if (mixed)
-    HIPCHK(launch_potrf_f32(Lc, p->d_order_eval, p->n_active, p->d_tx32, p->d_ty32, p->d_L32, p->d_Inv,
+    HIPCHK(launch_potrf_f32(Lc, p->d_order_eval, p->n_active, p->d_px32, p->d_py32, p->d_L32, p->d_Inv,
                             p->d_logdet, p->d_status));
   else
-    HIPCHK(launch_potrf_f64(Lc, p->d_order_eval, p->n_active, p->d_tx, p->d_ty, p->d_L64, p->d_Inv,
+    HIPCHK(launch_potrf_f64(Lc, p->d_order_eval, p->n_active, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
                             p->d_logdet, p->d_status));
   if (ev) HIPCHK(hipEventRecord(p->ev[1], p->stream));
   if (mixed) {
