@@ -12,11 +12,12 @@
 //      whose entries are 0, so padding rows form an identity block); lambda
 //      (and the padding's unit diagonal) is set by index when the diagonal
 //      block is moved to FP64;
-//   2. C^T -= L_J L_R^T over all previous columns, on MFMA from 64-byte row
-//      segments staged through LDS (conflict-free 16-byte operand reads);
+//   2. C^T -= L_J L_R^T over all previous columns, on MFMA from 128-byte row
+//      segments staged through two LDS buffers (loads for stage k+2 in flight
+//      while stage k is consumed; conflict-free 16-byte operand reads);
 //   3. the diagonal 64 x 64 blocks of the panel are factored in FP64 in LDS
-//      (right-looking, one barrier per column), inverted in FP64 into the
-//      free upper half of the same array, and the inverse is kept in LDS;
+//      (blocked in 16 x 16 tiles), inverted in FP64 into the free upper half
+//      of the same array, and the inverse is kept in LDS;
 //   4. the panel triangular solve X^T = L_JJ^{-1} C^T runs on MFMA with the
 //      accumulators themselves as the B operand (the contraction index is
 //      permuted to follow the accumulator layout), block row by block row
@@ -43,7 +44,7 @@ template <>
 struct Cfg<float> {
   typedef f32x4 acc_t;
   static constexpr int PB = 128;  // panel width
-  static constexpr int KC = 16;   // staged k per step (64 bytes of a row)
+  static constexpr int KC = 32;   // staged k per step (128 bytes of a row)
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -54,7 +55,7 @@ template <>
 struct Cfg<double> {
   typedef f64x4 acc_t;
   static constexpr int PB = 64;
-  static constexpr int KC = 8;
+  static constexpr int KC = 16;
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -90,6 +91,14 @@ __device__ __forceinline__ void load_crow4(const double* row, int g, double (&a)
   for (int v = 0; v < 4; ++v) a[v] = row[4 * v + g];
 }
 
+// Barrier that orders LDS only: unlike __syncthreads() it does not wait for
+// outstanding global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 constexpr int NT = 512;   // threads per workgroup (8 waves)
 constexpr int WR = 32;    // chunk rows per wave
 constexpr int NBJ = WR / 16;
@@ -101,13 +110,13 @@ struct Smem {
   static constexpr int PB = Cfg<T>::PB;
   static constexpr int KC = Cfg<T>::KC;
   static constexpr int VW = 16 / sizeof(T);   // elements per 16-byte vector
-  static constexpr int LDK = KC + VW;         // staged row stride (80 bytes)
+  static constexpr int LDK = KC + VW;         // staged row stride (144 bytes)
   static constexpr int LDI = 64 + VW;         // inverse row stride
   static constexpr int NSUB = PB / 64;
   static constexpr int STAGE = (PB + RCH) * LDK * (int)sizeof(T);
   static constexpr int L21 = 64 * LDI * (int)sizeof(T);
   static constexpr int DG = 64 * LDD * 8;
-  static constexpr int U0 = STAGE > DG ? STAGE : DG;
+  static constexpr int U0 = 2 * STAGE > DG ? 2 * STAGE : DG;  // two stage buffers
   static constexpr int U = U0 > L21 ? U0 : L21;
 };
 
@@ -142,57 +151,137 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB]
 // FP64 factorisation of the 64 x 64 block in Dg (lower part), in place,
 // followed by the inverse of the factor, stored transposed in the free upper
 // part: Inv[i][c] (i >= c) lives at Dg[c][i + 1].  Adds 2 sum log L_jj over
-// rows < nreal to *ld and records the first failing pivot (1-based global
-// row) in *bad.  All NT threads take part.
-__device__ void diag_factor_invert(double (*Dg)[LDD], double* piv, int nreal, int grow0, double& ld,
-                                   int& bad) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < 64; ++j) {
-    double p = Dg[j][j];
-    const bool ok = p > 0.0 && p < 1e300;
-    if (!ok) p = 1.0;
-    if (tid == 0) {
-      if (!ok && !bad) bad = grow0 + j + 1;
-      piv[j] = sqrt(p);
-      if (j < nreal) ld += log(p);
+// rows < nreal to ld and records the first failing pivot (1-based global
+// row) in bad (thread 0's copies).  All NT threads take part.
+//
+// Blocked in 16 x 16 tiles.  Factor, for each tile column kb:
+//   1. the diagonal tile by one wave, one row per lane, pivots and columns
+//      broadcast with lane shuffles (no barriers inside);
+//   2. the tiles below it by forward substitution, one row per thread;
+//   3. the trailing lower triangle updated with the new tile column.
+// Inverse: the four diagonal tiles first (one column per thread), then the
+// off-diagonal tiles by distance from the diagonal,
+//   Inv_ij = -Inv_ii * sum_{j<=k<i} L_ik Inv_kj.
+__device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], double* rdiag, int nreal,
+                                   int grow0, double& ld, int& bad) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int k0 = 16 * kb;
+    // 1. diagonal tile, wave 0: lane l owns entries (r, c) = (l / 4, l % 4 + 4 u).
+    //    One wave touches LDS in program order, so no barrier is needed.
+    if (w == 0) {
+      const int r = l >> 2;
+      for (int j = 0; j < 16; ++j) {
+        double p = Dg[k0 + j][k0 + j];
+        const bool ok = p > 0.0 && p < 1e300;
+        if (!ok) p = 1.0;
+        if (l == 0 && !ok && !bad) bad = grow0 + k0 + j + 1;
+        // 1/sqrt(p): hardware estimate refined by two Newton steps (error far below
+        // FP64 rounding), then sqrt(p) = p / sqrt(p)
+        double isp = __builtin_amdgcn_rsq(p);
+        isp = isp * (1.5 - 0.5 * p * isp * isp);
+        isp = isp * (1.5 - 0.5 * p * isp * isp);
+        const double sp = p * isp, ip = isp * isp;
+        if (l == 0) rdiag[k0 + j] = isp;
+        const double arj = Dg[k0 + r][k0 + j];
+        const double arjp = arj * ip;
+        double upd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = (l & 3) + 4 * u;
+          upd[u] = Dg[k0 + r][k0 + c] - arjp * Dg[k0 + c][k0 + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = (l & 3) + 4 * u;
+          if (c == j && r >= j) Dg[k0 + r][k0 + j] = r == j ? sp : arj * isp;
+          if (c > j && r >= c) Dg[k0 + r][k0 + c] = upd[u];
+        }
+      }
     }
-    const int m = 63 - j;
-    const double ip = 1.0 / p;
-    for (int e = tid; e < m * m; e += NT) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) Dg[i][k] -= Dg[i][j] * Dg[k][j] * ip;
+    __syncthreads();
+    if (kb == 3) break;
+    // 2. tiles below: rows i = k0 + 16 + t solve x L_kk^T = a; 16 lanes per row,
+    //    lane c keeps a_c, x_j is broadcast from lane j with a shuffle.
+    {
+      const int rows = 48 - k0;
+      for (int base = 4 * w; base < rows; base += 4 * (NT / 64)) {
+        const int ri = base + (l >> 4), c = l & 15;
+        const bool live = ri < rows;
+        const int i = k0 + 16 + (live ? ri : 0);
+        double av = Dg[i][k0 + c];
+        for (int j = 0; j < 16; ++j) {
+          const double xj = __shfl(av, (l & 48) + j, 64) * rdiag[k0 + j];
+          if (c == j) av = xj;
+          else if (c > j) av -= xj * Dg[k0 + c][k0 + j];
+        }
+        if (live) Dg[i][k0 + c] = av;
+      }
+    }
+    __syncthreads();
+    // 3. trailing update of the lower triangle: entry (i, k), k0+16 <= k <= i
+    {
+      const int m0 = 48 - k0;                       // trailing size
+      for (int e = tid; e < m0 * m0; e += NT) {
+        const int ii = e / m0, kk = e - ii * m0;
+        if (kk <= ii) {
+          const int i = k0 + 16 + ii, k = k0 + 16 + kk;
+          double sacc = 0.0;
+#pragma unroll 4
+          for (int m = 0; m < 16; ++m) sacc += Dg[i][k0 + m] * Dg[k][k0 + m];
+          Dg[i][k] -= sacc;
+        }
+      }
     }
     __syncthreads();
   }
-  // scale columns: L_ij = A_ij / sqrt(p_j), L_jj = sqrt(p_j)
-  for (int e = tid; e < 64 * 64; e += NT) {
-    const int i = e >> 6, j = e & 63;
-    if (j < i) Dg[i][j] /= piv[j];
-    else if (j == i) Dg[i][i] = piv[i];
+  // log det of this block: 2 sum log L_jj over real rows
+  if (w == 0) {
+    double t = l < nreal ? 2.0 * log(Dg[l][l]) : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (l == 0) ld += t;
+  }
+  // inverse of the four diagonal tiles: thread (b, c) computes column c of
+  // Inv_bb top-down, reading back its own earlier entries from LDS
+  if (tid < 64) {
+    const int o = 16 * (tid >> 4), c = tid & 15;
+    for (int r = c; r < 16; ++r) {
+      double sacc = r == c ? 1.0 : 0.0;
+      for (int m = c; m < r; ++m) sacc -= Dg[o + r][o + m] * Dg[o + c][o + m + 1];
+      Dg[o + c][o + r + 1] = sacc * rdiag[o + r];
+    }
   }
   __syncthreads();
-  // inverse, row by row: Inv[i][c] = (delta_ic - sum_{c<=k<i} L_ik Inv[k][c]) / L_ii
-  constexpr int NQ = NT / 64;
-  __shared__ double red[NQ][64];
-  const int c = tid & 63, q = tid >> 6;
-  for (int i = 0; i < 64; ++i) {
-    double s = 0.0;
-    for (int k = c + q; k < i; k += NQ) s += Dg[i][k] * Dg[c][k + 1];
-    red[q][c] = s;
+  // off-diagonal tiles, distance d = i - j
+  for (int d = 1; d < 4; ++d) {
+    const int np = 4 - d;  // tile pairs (i, j = i - d), j = 0..np-1
+    for (int e = tid; e < np * 256; e += NT) {
+      const int pj = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      const int j = pj, i = pj + d;
+      double sacc = 0.0;
+      // k = j: the diagonal tile Inv_jj is lower triangular (only m >= c stored)
+      for (int m = c; m < 16; ++m) sacc += Dg[16 * i + r][16 * j + m] * Dg[16 * j + c][16 * j + m + 1];
+      for (int k = j + 1; k < i; ++k) {
+#pragma unroll 4
+        for (int m = 0; m < 16; ++m) sacc += Dg[16 * i + r][16 * k + m] * Dg[16 * j + c][16 * k + m + 1];
+      }
+      Tb[pj][r][c] = sacc;
+    }
     __syncthreads();
-    if (q == 0 && c <= i) {
-      double r = 0.0;
-#pragma unroll
-      for (int qq = 0; qq < NQ; ++qq) r += red[qq][c];
-      const double t = (c == i ? 1.0 : 0.0) - r;
-      Dg[c][i + 1] = t / Dg[i][i];
+    for (int e = tid; e < np * 256; e += NT) {
+      const int pj = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      const int j = pj, i = pj + d;
+      double sacc = 0.0;
+      for (int m = 0; m <= r; ++m) sacc += Dg[16 * i + m][16 * i + r + 1] * Tb[pj][m][c];
+      Dg[16 * j + c][16 * i + r + 1] = -sacc;
     }
     __syncthreads();
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ desc,
+__global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order,
                                                  const ThetaDev* __restrict__ theta,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
@@ -210,7 +299,8 @@ __global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ 
 
   __shared__ __attribute__((aligned(16))) char smem_u[SM::U];
   __shared__ __attribute__((aligned(16))) T InvS[SM::NSUB][64 * LDI];
-  __shared__ double piv[64];
+  __shared__ double Tb[3][16][17];
+  __shared__ double rdiag[64];
   __shared__ T colx[PB], coly[PB];  // the current panel's column coordinates
 
   T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
@@ -284,9 +374,11 @@ __global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ 
       }
 
       // ---- 2. update: C^T -= L[c0:c0+PB, 0:c0] L[rows, 0:c0]^T
+      //      Two LDS stage buffers: while the MFMAs consume stage k, stage k+1 is
+      //      stored from registers and stage k+2 is loaded; one barrier per stage.
       if (c0 > 0) {
         // staging map: vector vi = tid + NT s -> (row vi / VPR, 16-byte column slot vi % VPR);
-        // rows [0, PB) are panel rows, the rest chunk rows
+        // rows [0, PB) are panel rows (stored negated), the rest chunk rows
         int goff[VPT];
         bool gok[VPT];
 #pragma unroll
@@ -298,13 +390,14 @@ __global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ 
           goff[s] = packed_rowoff32(gok[s] ? grow : 0) + cv * VW;
         }
         vec_t st[VPT];
+        auto gload = [&](int k0) {
 #pragma unroll
-        for (int s = 0; s < VPT; ++s) {
-          const vec_t v = *reinterpret_cast<const vec_t*>(L + goff[s]);
-          st[s] = gok[s] ? v : vec_t{};
-        }
-        for (int k0 = 0; k0 < c0; k0 += KC) {
-          __syncthreads();
+          for (int s = 0; s < VPT; ++s) {
+            const vec_t v = *reinterpret_cast<const vec_t*>(L + goff[s] + k0);
+            st[s] = gok[s] ? v : vec_t{};
+          }
+        };
+        auto lstore = [&](T* buf) {
 #pragma unroll
           for (int s = 0; s < VPT; ++s) {
             const int vi = tid + NT * s;
@@ -315,39 +408,50 @@ __global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ 
 #pragma unroll
               for (int e = 0; e < VW; ++e) p[e] = -p[e];
             }
-            if (vi < NVEC) *reinterpret_cast<vec_t*>(Ps + row * LDK + cv * VW) = v;  // Rs follows Ps
+            if (vi < NVEC) *reinterpret_cast<vec_t*>(buf + row * LDK + cv * VW) = v;
           }
-          __syncthreads();
-          if (k0 + KC < c0) {
-#pragma unroll
-            for (int s = 0; s < VPT; ++s) {
-              const vec_t v = *reinterpret_cast<const vec_t*>(L + goff[s] + k0 + KC);
-              st[s] = gok[s] ? v : vec_t{};
-            }
-          }
+        };
+        constexpr int SBUF = (PB + RCH) * LDK;  // elements per stage buffer
+        const int nst = c0 / KC;
+        gload(0);
+        lds_barrier();  // LDS free (previous phase done with smem_u)
+        lstore(Ps);
+        if (nst > 1) gload(KC);
+        lds_barrier();
+        for (int k = 0; k < nst; ++k) {
+          const T* Pk = Ps + (k & 1) * SBUF;
+          const T* Rk = Pk + PB * LDK;
           if (wact) {
-            // lane group g takes k = g * VW + s for the VW MFMA steps s
-            static_assert(KC / 4 == VW, "one 16-byte LDS read per operand block");
-            vec_t rb[NBJ];
+            // lane group g takes k = g (KC/4) + q VW + s: NQ 16-byte reads per operand
+            // block, VW MFMA steps per read
+            constexpr int NQ = KC / (4 * VW);
 #pragma unroll
-            for (int bj = 0; bj < NBJ; ++bj)
-              rb[bj] = *reinterpret_cast<const vec_t*>(Rs + (WR * w + 16 * bj + lr) * LDK + g * VW);
+            for (int q = 0; q < NQ; ++q) {
+              vec_t rb[NBJ];
 #pragma unroll
-            for (int h = 0; h < NBI; h += 4) {
-              vec_t pa[4];
+              for (int bj = 0; bj < NBJ; ++bj)
+                rb[bj] = *reinterpret_cast<const vec_t*>(Rk + (WR * w + 16 * bj + lr) * LDK + g * (KC / 4) +
+                                                         q * VW);
 #pragma unroll
-              for (int b = 0; b < 4; ++b)
-                pa[b] = *reinterpret_cast<const vec_t*>(Ps + (16 * (h + b) + lr) * LDK + g * VW);
-#pragma unroll
-              for (int s = 0; s < VW; ++s)
+              for (int h = 0; h < NBI; h += 4) {
+                vec_t pa[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
+                  pa[b] = *reinterpret_cast<const vec_t*>(Pk + (16 * (h + b) + lr) * LDK + g * (KC / 4) + q * VW);
 #pragma unroll
-                  for (int bj = 0; bj < NBJ; ++bj)
-                    acc[h + b][bj] = Cfg<T>::mma(reinterpret_cast<const T*>(&pa[b])[s],
-                                                 reinterpret_cast<const T*>(&rb[bj])[s], acc[h + b][bj]);
+                for (int s = 0; s < VW; ++s)
+#pragma unroll
+                  for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int bj = 0; bj < NBJ; ++bj)
+                      acc[h + b][bj] = Cfg<T>::mma(reinterpret_cast<const T*>(&pa[b])[s],
+                                                   reinterpret_cast<const T*>(&rb[bj])[s], acc[h + b][bj]);
+              }
             }
           }
+          if (k + 1 < nst) lstore(Ps + ((k + 1) & 1) * SBUF);
+          if (k + 2 < nst) gload((k + 2) * KC);
+          lds_barrier();
         }
       }
 
@@ -366,7 +470,7 @@ __global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ 
         __syncthreads();
         if (tid < 64) Dg[tid][tid] = c0 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
         __syncthreads();
-        diag_factor_invert(Dg, piv, n - c0, c0, ld, bad);
+        diag_factor_invert(Dg, Tb, rdiag, n - c0, c0, ld, bad);
         for (int e = tid; e < 64 * 64; e += NT) {
           const int i = e >> 6, j = e & 63;
           L[packed_rowoff32(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
@@ -436,7 +540,7 @@ __global__ __launch_bounds__(NT, 4) void k_potrf(const SubsetDesc* __restrict__ 
             __syncthreads();
             if (tid < 64) Dg[tid][tid] = c0 + 64 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
             __syncthreads();
-            diag_factor_invert(Dg, piv, n - c0 - 64, c0 + 64, ld, bad);
+            diag_factor_invert(Dg, Tb, rdiag, n - c0 - 64, c0 + 64, ld, bad);
             for (int e = tid; e < 64 * 64; e += NT) {
               const int i = e >> 6, j = e & 63;
               L[packed_rowoff32(c0 + 64 + i) + c0 + 64 + j] = j <= i ? (T)Dg[i][j] : (T)0;
