@@ -68,16 +68,20 @@ hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, 
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
                             const double* cy, double* Lbuf, double* Inv, double* logdet,
                             int32_t* status);
-hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, const float* Lbuf,
-                               const double* Inv, const double* rhs_train, const double* rhs_pad,
-                               double* z, double* rhs2);
-hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, const double* Lbuf,
-                               const double* Inv, const double* rhs_train, const double* rhs_pad,
-                               double* z, double* rhs2);
-hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, const float* Lbuf,
-                               const double* Inv, const double* z, double* x, double* alpha_accum);
-hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, const double* Lbuf,
-                               const double* Inv, const double* z, double* x, double* alpha_accum);
+// max_npad: the largest padded size among the launched subsets (selects the
+// per-thread register budget of the solve kernels).
+hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const float* Lbuf, const double* Inv, const double* rhs_train,
+                               const double* rhs_pad, double* z, double* rhs2);
+hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const double* Lbuf, const double* Inv, const double* rhs_train,
+                               const double* rhs_pad, double* z, double* rhs2);
+hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const float* Lbuf, const double* Inv, const double* z, double* x,
+                               double* alpha_accum);
+hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const double* Lbuf, const double* Inv, const double* z, double* x,
+                               double* alpha_accum);
 hipError_t launch_residual(const Launch& L, const int2* items, int n_items, const double* tx,
                            const double* ty, const double* yT, const double* alpha, double* r);
 hipError_t launch_predict_val(const Launch& L, const int2* items, int n_items, const double* tx,

@@ -28,6 +28,7 @@ struct pcv_problem {
   std::vector<double> ynorm2;       // S: ||y_T||^2
   int64_t nnzT = 0, nnzV = 0, nP = 0, nL = 0, nInv = 0, n_val_total = 0;
   int32_t max_train = 0;
+  int32_t max_npad = 0;
   int32_t n_active = 0;
 
   // device copies

@@ -4,12 +4,15 @@
 //   (the factorisation k_potrf<T> lives in pcv_potrf.hip)
 //   k_trsv_fwd<T>   forward substitution L z = b (FP64 accumulation)
 //   k_trsv_bwd<T>   backward substitution L^T x = z, optionally alpha += x
+//                   (both right-looking over 64-column blocks, see below)
 //   k_residual      r = y_T - (Sigma + lambda I) alpha in FP64, the matrix
 //                   regenerated from FP64 coordinates (refinement residual)
 //   k_predict_val   kriging predictor eq. (3) at the validation points and
 //                   squared errors of eq. (4), FP64
 //   k_reduce        per-subset SSPE z_i and the sum of eq. (7) / Algorithm 1
 //                   (fixed-order compensated FP64 sums)
+#include <type_traits>
+
 #include "pcv_device.h"
 
 namespace pcv {
@@ -76,91 +79,133 @@ struct Tile {
 };
 
 // ---------------------------------------------------------------------------
-// Forward substitution L z = b, one workgroup per subset, FP64 accumulation.
-// Block J: t = b_J - L[J, 0:J] z[0:J]  (each wave 16 rows, lanes over k),
-//          z_J = Inv_J t.
-// b is the training vector (rhs_train, length n, 0 beyond) or a padded
-// vector (rhs_pad, length npad).
+// Triangular solves with the packed factor, one workgroup of 512 threads per
+// subset, FP64 accumulation.  Right-looking by 64-column blocks: the 64 x 64
+// inverse of the diagonal block is staged in LDS, the block's unknowns are
+// formed from it, and every thread then subtracts their contribution from the
+// partial sums it owns (kept in registers):
+//   forward  L z = b:   thread owns rows r = tid + 512 i, streams the row
+//                       segment L[r, c0:c0+64] (256 bytes in FP32);
+//   backward L^T x = z: thread owns column quads q = tid + 512 i (columns
+//                       4q..4q+3), streams L[c0+k, 4q:4q+4] for the block's
+//                       64 rows (coalesced across threads).
+// MR / MQ bound the rows / quads per thread (npad <= 512 MR).
 // ---------------------------------------------------------------------------
+constexpr int SNT = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd(const SubsetDesc* __restrict__ desc,
-                                                  const int32_t* __restrict__ order,
-                                                  const T* __restrict__ Lbuf,
-                                                  const double* __restrict__ Invbuf,
-                                                  const double* __restrict__ rhs_train,
-                                                  const double* __restrict__ rhs_pad,
-                                                  double* __restrict__ zbuf,
-                                                  double* __restrict__ rhs2out) {
-  __shared__ double t[TB];
-  __shared__ double b2s[4];
+struct SVec;
+template <>
+struct SVec<float> {
+  typedef float4 type;
+  static constexpr int W = 4;
+};
+template <>
+struct SVec<double> {
+  typedef double2 type;
+  static constexpr int W = 2;
+};
+
+__device__ __forceinline__ void stage_inv(double (*IL)[65], const double* __restrict__ Iblk, int tid) {
+  for (int e = tid; e < 2048; e += SNT) {
+    const double2 v = reinterpret_cast<const double2*>(Iblk)[e];
+    const int i = (2 * e) >> 6, j = (2 * e) & 63;
+    IL[i][j] = v.x;
+    IL[i][j + 1] = v.y;
+  }
+}
+
+template <typename T, int MR>
+__global__ __launch_bounds__(512, 1) void k_trsv_fwd(const SubsetDesc* __restrict__ desc,
+                                                     const int32_t* __restrict__ order,
+                                                     const T* __restrict__ Lbuf,
+                                                     const double* __restrict__ Invbuf,
+                                                     const double* __restrict__ rhs_train,
+                                                     const double* __restrict__ rhs_pad,
+                                                     double* __restrict__ zbuf,
+                                                     double* __restrict__ rhs2out) {
+  typedef typename SVec<T>::type vec_t;
+  constexpr int VW = SVec<T>::W;
+  __shared__ double IL[64][65];
+  __shared__ double tJ[64], zJ[64];
+  __shared__ double b2s[SNT / 64];
   const int sidx = order[blockIdx.x];
   const SubsetDesc D = desc[sidx];
   const int n = D.n, npad = D.npad, nb = npad / TB;
   const T* __restrict__ L = Lbuf + D.offL;
   const double* __restrict__ Inv = Invbuf + D.offInv;
   double* __restrict__ z = zbuf + D.offP;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tid = threadIdx.x;
+  double t[MR];
   double b2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    const int row = tid + SNT * i;
+    double b = 0.0;
+    if (row < npad) b = rhs_pad ? rhs_pad[D.offP + row] : (row < n ? rhs_train[D.offT + row] : 0.0);
+    t[i] = b;
+    b2 += b * b;
+  }
   for (int J = 0; J < nb; ++J) {
     const int c0 = J * TB;
-    double acc[16];
+    stage_inv(IL, Inv + (int64_t)J * TB * TB, tid);
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) acc[rr] = 0.0;
-    for (int k = l; k < c0; k += 64) {
-      const double zk = z[k];
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) acc[rr] += (double)L[packed_rowoff(c0 + 16 * w + rr) + k] * zk;
-    }
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-      double s = acc[rr];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (l == rr) {
-        const int row = c0 + 16 * w + rr;
-        double b;
-        if (rhs_pad)
-          b = rhs_pad[D.offP + row];
-        else
-          b = row < n ? rhs_train[D.offT + row] : 0.0;
-        t[16 * w + rr] = b - s;
-        b2 += b * b;
-      }
+    for (int i = 0; i < MR; ++i) {
+      const int row = tid + SNT * i;
+      if (row >= c0 && row < c0 + TB) tJ[row - c0] = t[i];
     }
     __syncthreads();
     if (tid < TB) {
-      const double* Ir = Inv + (int64_t)J * TB * TB + tid * TB;
       double s = 0.0;
-      for (int j = 0; j <= tid; ++j) s += Ir[j] * t[j];
+      for (int j = 0; j <= tid; ++j) s += IL[tid][j] * tJ[j];
+      zJ[tid] = s;
       z[c0 + tid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+      const int row = tid + SNT * i;
+      if (row >= c0 + TB && row < npad) {
+        const vec_t* Lr = reinterpret_cast<const vec_t*>(L + packed_rowoff32(row) + c0);
+        vec_t v[TB / VW];
+#pragma unroll
+        for (int k = 0; k < TB / VW; ++k) v[k] = Lr[k];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < TB / VW; ++k) {
+          const T* e = reinterpret_cast<const T*>(&v[k]);
+#pragma unroll
+          for (int u = 0; u < VW; ++u) acc += (double)e[u] * zJ[k * VW + u];
+        }
+        t[i] -= acc;
+      }
     }
     __syncthreads();
   }
   if (rhs2out) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) b2 += __shfl_xor(b2, off, 64);
-    if (l == 0) b2s[w] = b2;
+    if ((tid & 63) == 0) b2s[tid >> 6] = b2;
     __syncthreads();
-    if (tid == 0) rhs2out[sidx] = (b2s[0] + b2s[1]) + (b2s[2] + b2s[3]);
+    if (tid == 0) {
+      double s = 0.0;
+      for (int k = 0; k < SNT / 64; ++k) s += b2s[k];
+      rhs2out[sidx] = s;
+    }
   }
 }
 
-// ---------------------------------------------------------------------------
-// Backward substitution L^T x = z, one workgroup per subset.
-// Block J (descending): t = z_J - L[J+1:, J]^T x[J+1:]  (lanes over the TB
-// columns, waves over rows), x_J = Inv_J^T t.  If alpha_accum is given,
-// alpha += x as each block is finished.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_bwd(const SubsetDesc* __restrict__ desc,
-                                                  const int32_t* __restrict__ order,
-                                                  const T* __restrict__ Lbuf,
-                                                  const double* __restrict__ Invbuf,
-                                                  const double* __restrict__ zbuf,
-                                                  double* __restrict__ xbuf,
-                                                  double* __restrict__ alpha_accum) {
-  __shared__ double part[4][TB];
-  __shared__ double t[TB];
+template <typename T, int MQ>
+__global__ __launch_bounds__(512, 1) void k_trsv_bwd(const SubsetDesc* __restrict__ desc,
+                                                     const int32_t* __restrict__ order,
+                                                     const T* __restrict__ Lbuf,
+                                                     const double* __restrict__ Invbuf,
+                                                     const double* __restrict__ zbuf,
+                                                     double* __restrict__ xbuf,
+                                                     double* __restrict__ alpha_accum) {
+  typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type q_t;
+  __shared__ double IL[64][65];
+  __shared__ double tJ[64], xJ[64];
   const int sidx = order[blockIdx.x];
   const SubsetDesc D = desc[sidx];
   const int npad = D.npad, nb = npad / TB;
@@ -168,33 +213,53 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const SubsetDesc* __restrict__
   const double* __restrict__ Inv = Invbuf + D.offInv;
   const double* __restrict__ z = zbuf + D.offP;
   double* __restrict__ x = xbuf + D.offP;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tid = threadIdx.x;
+  double t[MQ][4];
+#pragma unroll
+  for (int i = 0; i < MQ; ++i) {
+    const int c = 4 * (tid + SNT * i);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[i][u] = c + u < npad ? z[c + u] : 0.0;
+  }
   for (int J = nb - 1; J >= 0; --J) {
     const int c0 = J * TB;
-    double acc = 0.0;
-    int r = c0 + TB + w;
-    for (; r + 12 < npad; r += 16) {
-      const double x0 = x[r], x1 = x[r + 4], x2 = x[r + 8], x3 = x[r + 12];
-      const double l0 = (double)L[packed_rowoff(r) + c0 + l];
-      const double l1 = (double)L[packed_rowoff(r + 4) + c0 + l];
-      const double l2 = (double)L[packed_rowoff(r + 8) + c0 + l];
-      const double l3 = (double)L[packed_rowoff(r + 12) + c0 + l];
-      acc += l0 * x0;
-      acc += l1 * x1;
-      acc += l2 * x2;
-      acc += l3 * x3;
+    stage_inv(IL, Inv + (int64_t)J * TB * TB, tid);
+#pragma unroll
+    for (int i = 0; i < MQ; ++i) {
+      const int c = 4 * (tid + SNT * i);
+      if (c >= c0 && c < c0 + TB) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tJ[c - c0 + u] = t[i][u];
+      }
     }
-    for (; r < npad; r += 4) acc += (double)L[packed_rowoff(r) + c0 + l] * x[r];
-    part[w][l] = acc;
-    __syncthreads();
-    if (tid < TB) t[tid] = z[c0 + tid] - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
     __syncthreads();
     if (tid < TB) {
-      const double* I0 = Inv + (int64_t)J * TB * TB;
       double s = 0.0;
-      for (int j = tid; j < TB; ++j) s += I0[j * TB + tid] * t[j];
+      for (int i = tid; i < TB; ++i) s += IL[i][tid] * tJ[i];
+      xJ[tid] = s;
       x[c0 + tid] = s;
       if (alpha_accum) alpha_accum[D.offP + c0 + tid] += s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MQ; ++i) {
+      const int c = 4 * (tid + SNT * i);
+      if (c < c0) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 16
+        for (int r = 0; r < TB; ++r) {
+          const q_t v = *reinterpret_cast<const q_t*>(L + packed_rowoff32(c0 + r) + c);
+          const double xr = xJ[r];
+          a0 += (double)v.x * xr;
+          a1 += (double)v.y * xr;
+          a2 += (double)v.z * xr;
+          a3 += (double)v.w * xr;
+        }
+        t[i][0] -= a0;
+        t[i][1] -= a1;
+        t[i][2] -= a2;
+        t[i][3] -= a3;
+      }
     }
     __syncthreads();
   }
@@ -345,40 +410,48 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
 
 // ------------------------------------------------------------- launchers --
 template <typename T>
-static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items, const T* Lbuf,
+static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items, int max_npad, const T* Lbuf,
                              const double* Inv, const double* rt, const double* rp, double* z,
                              double* rhs2) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                     rt, rp, z, rhs2);
+  if (max_npad <= 4096)
+    hipLaunchKernelGGL((k_trsv_fwd<T, 8>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
+                       rt, rp, z, rhs2);
+  else
+    hipLaunchKernelGGL((k_trsv_fwd<T, 32>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
+                       rt, rp, z, rhs2);
   return hipGetLastError();
 }
-hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, const float* Lbuf,
-                               const double* Inv, const double* rt, const double* rp, double* z,
-                               double* rhs2) {
-  return fwd_launch<float>(L, order, n_items, Lbuf, Inv, rt, rp, z, rhs2);
+hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const float* Lbuf, const double* Inv, const double* rt, const double* rp,
+                               double* z, double* rhs2) {
+  return fwd_launch<float>(L, order, n_items, max_npad, Lbuf, Inv, rt, rp, z, rhs2);
 }
-hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, const double* Lbuf,
-                               const double* Inv, const double* rt, const double* rp, double* z,
-                               double* rhs2) {
-  return fwd_launch<double>(L, order, n_items, Lbuf, Inv, rt, rp, z, rhs2);
+hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const double* Lbuf, const double* Inv, const double* rt, const double* rp,
+                               double* z, double* rhs2) {
+  return fwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, rt, rp, z, rhs2);
 }
 
 template <typename T>
-static hipError_t bwd_launch(const Launch& Lc, const int32_t* order, int n_items, const T* Lbuf,
+static hipError_t bwd_launch(const Launch& Lc, const int32_t* order, int n_items, int max_npad, const T* Lbuf,
                              const double* Inv, const double* z, double* x, double* acc) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                     z, x, acc);
+  if (max_npad <= 4096)
+    hipLaunchKernelGGL((k_trsv_bwd<T, 2>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
+                       z, x, acc);
+  else
+    hipLaunchKernelGGL((k_trsv_bwd<T, 8>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
+                       z, x, acc);
   return hipGetLastError();
 }
-hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, const float* Lbuf,
-                               const double* Inv, const double* z, double* x, double* acc) {
-  return bwd_launch<float>(L, order, n_items, Lbuf, Inv, z, x, acc);
+hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const float* Lbuf, const double* Inv, const double* z, double* x, double* acc) {
+  return bwd_launch<float>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc);
 }
-hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, const double* Lbuf,
-                               const double* Inv, const double* z, double* x, double* acc) {
-  return bwd_launch<double>(L, order, n_items, Lbuf, Inv, z, x, acc);
+hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
+                               const double* Lbuf, const double* Inv, const double* z, double* x, double* acc) {
+  return bwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc);
 }
 
 hipError_t launch_residual(const Launch& Lc, const int2* items, int n_items, const double* tx,

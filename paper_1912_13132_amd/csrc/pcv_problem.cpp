@@ -201,6 +201,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     offL += packed_size(d.npad);
     offInv += (int64_t)d.npad * TB;
     p->max_train = std::max(p->max_train, d.n);
+    p->max_npad = std::max(p->max_npad, d.npad);
     if (d.m > 0) {
       p->active[i] = 1;
       act_ids.push_back(i);
@@ -338,8 +339,8 @@ pcv_status factor_solve64(pcv_problem* p, const ThetaDev* d_theta, const int32_t
                           int32_t* statusb) {
   Launch Lc{p->stream, p->d_desc, d_theta};
   HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_px64, p->d_py64, Lb, Invb, logdetb, statusb));
-  HIPCHK(launch_trsv_fwd_f64(Lc, d_order, count, Lb, Invb, p->d_yT, nullptr, zb, nullptr));
-  HIPCHK(launch_trsv_bwd_f64(Lc, d_order, count, Lb, Invb, zb, alphab, nullptr));
+  HIPCHK(launch_trsv_fwd_f64(Lc, d_order, count, p->max_npad, Lb, Invb, p->d_yT, nullptr, zb, nullptr));
+  HIPCHK(launch_trsv_bwd_f64(Lc, d_order, count, p->max_npad, Lb, Invb, zb, alphab, nullptr));
   return PCV_OK;
 }
 
@@ -364,14 +365,14 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
                             p->d_logdet, p->d_status));
   if (ev) HIPCHK(hipEventRecord(p->ev[1], p->stream));
   if (mixed) {
-    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, p->d_yT, nullptr, p->d_z,
+    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_yT, nullptr, p->d_z,
                                nullptr));
-    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, p->d_z, p->d_alpha,
+    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z, p->d_alpha,
                                nullptr));
   } else {
-    HIPCHK(launch_trsv_fwd_f64(Lc, p->d_order_eval, p->n_active, p->d_L64, p->d_Inv, p->d_yT, nullptr, p->d_z,
+    HIPCHK(launch_trsv_fwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_yT, nullptr, p->d_z,
                                nullptr));
-    HIPCHK(launch_trsv_bwd_f64(Lc, p->d_order_eval, p->n_active, p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
+    HIPCHK(launch_trsv_bwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
                                nullptr));
   }
   if (ev) HIPCHK(hipEventRecord(p->ev[2], p->stream));
@@ -379,9 +380,9 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   for (int it = 0; it < sweeps; ++it) {
     HIPCHK(launch_residual(Lc, p->d_row_items, (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT,
                            p->d_alpha, p->d_r));
-    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, nullptr, p->d_r, p->d_z,
+    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, nullptr, p->d_r, p->d_z,
                                p->d_rhs2));
-    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->d_L32, p->d_Inv, p->d_z, p->d_x,
+    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z, p->d_x,
                                p->d_alpha));
   }
   if (ev) HIPCHK(hipEventRecord(p->ev[3], p->stream));
