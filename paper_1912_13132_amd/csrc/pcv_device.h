@@ -22,6 +22,7 @@ struct SubsetDesc {
   int64_t offP;    // padded vectors (z, alpha, r, x)              [npad]
   int64_t offL;    // packed tile-row lower factor                 [packed_size(npad)]
   int64_t offInv;  // inverse diagonal blocks, FP64                [npad * TB]
+  int64_t offPC;   // residual column partials, FP64               [TB * nb (nb - 1) / 2]
   int32_t n, m, npad, id;
 };
 
@@ -82,8 +83,12 @@ hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_item
 hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const double* Lbuf, const double* Inv, const double* z, double* x,
                                double* alpha_accum);
-hipError_t launch_residual(const Launch& L, const int2* items, int n_items, const double* tx,
-                           const double* ty, const double* yT, const double* alpha, double* r);
+// Refinement residual r = y_T - (Sigma + lambda I) alpha, each symmetric entry
+// generated once: tile items (subset, row block I) sorted by work, and row
+// items (subset, row block) for the fixed-order reduction.
+hipError_t launch_residual(const Launch& L, const int2* tile_items, int n_tile_items, const int2* row_items,
+                           int n_row_items, const double* tx, const double* ty, const double* yT,
+                           const double* alpha, double* rrow, double* pcol, double* r);
 hipError_t launch_predict_val(const Launch& L, const int2* items, int n_items, const double* tx,
                               const double* ty, const double* vx, const double* vy,
                               const double* yV, const double* alpha, double* yhat, double* err);

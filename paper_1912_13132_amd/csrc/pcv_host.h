@@ -22,6 +22,7 @@ struct pcv_problem {
   std::vector<int32_t> order_eval;  // active subsets, largest n^3 first
   std::vector<int32_t> order_all;   // subsets with >= 1 training point, largest first
   std::vector<int2> row_items_eval; // (subset, 64-row block) over order_eval
+  std::vector<int2> tile_items;     // (subset, row block I), by decreasing I (residual tiles)
   std::vector<int2> val_items;      // (subset, 64-point validation block)
   std::vector<double> core_rect;    // S x 4, empty when not given
   std::vector<double> centroid;     // S x 2
@@ -37,6 +38,9 @@ struct pcv_problem {
   int32_t* d_order_all = nullptr;
   int32_t* d_active = nullptr;
   int2* d_row_items = nullptr;
+  int2* d_tile_items = nullptr;
+  double *d_rrow = nullptr, *d_pcol = nullptr;
+  int64_t nPC = 0;
   int2* d_val_items = nullptr;
   double *d_tx = nullptr, *d_ty = nullptr, *d_yT = nullptr;
   // factorisation coordinates, padded to npad per subset with +inf (offP)

@@ -5,8 +5,9 @@
 //   k_trsv_fwd<T>   forward substitution L z = b (FP64 accumulation)
 //   k_trsv_bwd<T>   backward substitution L^T x = z, optionally alpha += x
 //                   (both right-looking over 64-column blocks, see below)
-//   k_residual      r = y_T - (Sigma + lambda I) alpha in FP64, the matrix
-//                   regenerated from FP64 coordinates (refinement residual)
+//   k_residual_*    r = y_T - (Sigma + lambda I) alpha in FP64, the matrix
+//                   regenerated from FP64 coordinates (refinement residual;
+//                   symmetric tiles, fixed-order partial sums)
 //   k_predict_val   kriging predictor eq. (3) at the validation points and
 //                   squared errors of eq. (4), FP64
 //   k_reduce        per-subset SSPE z_i and the sum of eq. (7) / Algorithm 1
@@ -267,40 +268,124 @@ __global__ __launch_bounds__(512, 1) void k_trsv_bwd(const SubsetDesc* __restric
 
 // ---------------------------------------------------------------------------
 // Refinement residual r = y_T - (Sigma + lambda I) alpha in FP64, the matrix
-// regenerated from FP64 coordinates.  Item = (subset, block of 64 rows);
-// thread (row, phase) sums columns c = phase mod 4.
+// regenerated from FP64 coordinates.  Sigma is symmetric, so every entry is
+// generated once: the workgroup of row block I visits tiles (I, J), J <= I
+// (wave w takes J = w, w + 4, ...; lane (ri, cj) an 8 x 8 sub-tile), and
+// forms both Sigma_IJ alpha_J (row sums, kept) and Sigma_IJ^T alpha_I (column
+// sums for block J, written to a partial buffer).  A second kernel adds the
+// partials in a fixed order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_residual(const SubsetDesc* __restrict__ desc,
-                                                  const int2* __restrict__ items,
-                                                  const ThetaDev* __restrict__ theta,
-                                                  const double* __restrict__ tx,
-                                                  const double* __restrict__ ty,
-                                                  const double* __restrict__ yT,
-                                                  const double* __restrict__ alphabuf,
-                                                  double* __restrict__ rbuf) {
+__global__ __launch_bounds__(256, 2) void k_residual_tiles(const SubsetDesc* __restrict__ desc,
+                                                        const int2* __restrict__ items,
+                                                        const ThetaDev* __restrict__ theta,
+                                                        const double* __restrict__ tx,
+                                                        const double* __restrict__ ty,
+                                                        const double* __restrict__ alphabuf,
+                                                        double* __restrict__ rrow,
+                                                        double* __restrict__ pcol) {
   __shared__ double red[4][64];
   const int2 it = items[blockIdx.x];
   const SubsetDesc D = desc[it.x];
-  const int n = D.n;
-  const int tid = threadIdx.x, q = tid >> 6, l = tid & 63;
-  const int row = it.y * 64 + l;
+  const int I = it.y, n = D.n;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int ri = l >> 3, cj = l & 7;
   const int cov = theta->cov;
-  const double ir = theta->inv_range, lam = theta->lambda;
+  const double ir = theta->inv_range;
   const double* __restrict__ X = tx + D.offT;
   const double* __restrict__ Y = ty + D.offT;
   const double* __restrict__ a = alphabuf + D.offP;
-  double s = 0.0;
-  if (row < n) {
-    const double xr = X[row], yr = Y[row];
-    for (int c = q; c < n; c += 4) s += corr(cov, dist(xr - X[c], yr - Y[c]), ir) * a[c];
+  double xi[8], yi[8], ai[8];
+  bool vi[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int row = 64 * I + 8 * ri + u;
+    vi[u] = row < n;
+    const int rc = vi[u] ? row : 0;
+    xi[u] = X[rc];
+    yi[u] = Y[rc];
+    ai[u] = vi[u] ? a[row] : 0.0;
   }
-  red[q][l] = s;
+  double rowacc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) rowacc[u] = 0.0;
+  for (int J = w; J <= I; J += 4) {
+    double xj[8], yj[8], aj[8];
+    bool vj[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int col = 64 * J + 8 * cj + v;
+      vj[v] = col < n;
+      const int cc = vj[v] ? col : 0;
+      xj[v] = X[cc];
+      yj[v] = Y[cc];
+      aj[v] = vj[v] ? a[col] : 0.0;
+    }
+    double rp[8], cp[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rp[u] = cp[u] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const double dx = xi[u] - xj[v], dy = yi[u] - yj[v];
+        double c = corr(cov, dist(dx, dy), ir);
+        c = (vi[u] && vj[v]) ? c : 0.0;
+        rp[u] += c * aj[v];
+        cp[v] += c * ai[u];
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      double t = rp[u];
+      t += __shfl_xor(t, 1, 64);
+      t += __shfl_xor(t, 2, 64);
+      t += __shfl_xor(t, 4, 64);
+      rowacc[u] += t;
+    }
+    if (J < I) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        double t = cp[v];
+        t += __shfl_xor(t, 8, 64);
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        cp[v] = t;
+      }
+      if (ri == 0) {
+        double* dst = pcol + D.offPC + ((int64_t)I * (I - 1) / 2 + J) * 64 + 8 * cj;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) dst[v] = cp[v];
+      }
+    }
+  }
+  if (cj == 0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) red[w][8 * ri + u] = rowacc[u];
+  }
   __syncthreads();
-  if (q == 0 && row < D.npad) {
-    double r = 0.0;
-    if (row < n) r = yT[D.offT + row] - ((red[0][l] + red[1][l]) + (red[2][l] + red[3][l])) - lam * a[row];
-    rbuf[D.offP + row] = r;
+  if (tid < 64) rrow[D.offP + 64 * I + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+// r_j = y_j - lambda alpha_j - (row sums of block J) - sum_{I > J} (column
+// sums of tile (I, J)), added in increasing I.  Item = (subset, row block J).
+__global__ __launch_bounds__(64) void k_residual_reduce(const SubsetDesc* __restrict__ desc,
+                                                        const int2* __restrict__ items,
+                                                        const ThetaDev* __restrict__ theta,
+                                                        const double* __restrict__ yT,
+                                                        const double* __restrict__ alphabuf,
+                                                        const double* __restrict__ rrow,
+                                                        const double* __restrict__ pcol,
+                                                        double* __restrict__ rbuf) {
+  const int2 it = items[blockIdx.x];
+  const SubsetDesc D = desc[it.x];
+  const int J = it.y, n = D.n, nb = D.npad / TB;
+  const int row = 64 * J + threadIdx.x;
+  double r = 0.0;
+  if (row < n) {
+    double s = rrow[D.offP + row];
+    for (int I = J + 1; I < nb; ++I) s += pcol[D.offPC + ((int64_t)I * (I - 1) / 2 + J) * 64 + threadIdx.x];
+    r = yT[D.offT + row] - theta->lambda * alphabuf[D.offP + row] - s;
   }
+  rbuf[D.offP + row] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -454,11 +539,14 @@ hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_item
   return bwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc);
 }
 
-hipError_t launch_residual(const Launch& Lc, const int2* items, int n_items, const double* tx,
-                           const double* ty, const double* yT, const double* alpha, double* r) {
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, items, Lc.theta, tx,
-                     ty, yT, alpha, r);
+hipError_t launch_residual(const Launch& Lc, const int2* tile_items, int n_tile_items, const int2* row_items,
+                           int n_row_items, const double* tx, const double* ty, const double* yT,
+                           const double* alpha, double* rrow, double* pcol, double* r) {
+  if (n_tile_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual_tiles, dim3(n_tile_items), dim3(256), 0, Lc.stream, Lc.desc, tile_items,
+                     Lc.theta, tx, ty, alpha, rrow, pcol);
+  hipLaunchKernelGGL(k_residual_reduce, dim3(n_row_items), dim3(64), 0, Lc.stream, Lc.desc, row_items,
+                     Lc.theta, yT, alpha, rrow, pcol, r);
   return hipGetLastError();
 }
 

@@ -182,7 +182,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   p->ynorm2.assign(S, 0.0);
   if (core_rect) p->core_rect.assign(core_rect, core_rect + 4 * (size_t)S);
 
-  int64_t offT = 0, offV = 0, offP = 0, offL = 0, offInv = 0;
+  int64_t offT = 0, offV = 0, offP = 0, offL = 0, offInv = 0, offPC = 0;
   std::vector<int32_t> act_ids, all_ids;
   for (int32_t i = 0; i < S; ++i) {
     SubsetDesc& d = p->desc[i];
@@ -195,11 +195,16 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     d.offP = offP;
     d.offL = offL;
     d.offInv = offInv;
+    d.offPC = offPC;
     offT += d.n;
     offV += d.m;
     offP += d.npad;
     offL += packed_size(d.npad);
     offInv += (int64_t)d.npad * TB;
+    {
+      const int64_t nbk = d.npad / TB;
+      offPC += (int64_t)TB * nbk * (nbk - 1) / 2;
+    }
     p->max_train = std::max(p->max_train, d.n);
     p->max_npad = std::max(p->max_npad, d.npad);
     if (d.m > 0) {
@@ -214,6 +219,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   p->nP = offP;
   p->nL = offL;
   p->nInv = offInv;
+  p->nPC = offPC;
   p->n_active = (int32_t)act_ids.size();
   p->order_eval = lpt_order(p->desc, act_ids);
   p->order_all = lpt_order(p->desc, all_ids);
@@ -221,6 +227,9 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     for (int rb = 0; rb < p->desc[i].npad / TB; ++rb) p->row_items_eval.push_back(make_int2(i, rb));
     for (int vb = 0; vb < (p->desc[i].m + 63) / 64; ++vb) p->val_items.push_back(make_int2(i, vb));
   }
+  p->tile_items = p->row_items_eval;
+  std::stable_sort(p->tile_items.begin(), p->tile_items.end(),
+                   [](const int2& a, const int2& b) { return a.y > b.y; });
 
   // per-subset panels, centred on the subset's training centroid (FP64)
   std::vector<double> tx(offT), ty(offT), yT(offT), vx(offV), vy(offV), yV(offV);
@@ -278,6 +287,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(upload(p, &p->d_order_all, p->order_all));
   TRY(upload(p, &p->d_active, p->active));
   TRY(upload(p, &p->d_row_items, p->row_items_eval));
+  TRY(upload(p, &p->d_tile_items, p->tile_items));
   TRY(upload(p, &p->d_val_items, p->val_items));
   TRY(upload(p, &p->d_tx, tx));
   TRY(upload(p, &p->d_ty, ty));
@@ -293,6 +303,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(dalloc(p, &p->d_x, (size_t)p->nP));
   TRY(dalloc(p, &p->d_alpha, (size_t)p->nP));
   TRY(dalloc(p, &p->d_r, (size_t)p->nP));
+  TRY(dalloc(p, &p->d_rrow, (size_t)p->nP));
+  TRY(dalloc(p, &p->d_pcol, (size_t)std::max<int64_t>(p->nPC, 1)));
   TRY(dalloc(p, &p->d_rhs2, (size_t)S));
   TRY(dalloc(p, &p->d_yhat, (size_t)p->nnzV));
   TRY(dalloc(p, &p->d_err, (size_t)p->nnzV));
@@ -378,8 +390,9 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   if (ev) HIPCHK(hipEventRecord(p->ev[2], p->stream));
   const int sweeps = mixed ? p->opt.max_refine : 0;
   for (int it = 0; it < sweeps; ++it) {
-    HIPCHK(launch_residual(Lc, p->d_row_items, (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT,
-                           p->d_alpha, p->d_r));
+    HIPCHK(launch_residual(Lc, p->d_tile_items, (int)p->tile_items.size(), p->d_row_items,
+                           (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT, p->d_alpha, p->d_rrow,
+                           p->d_pcol, p->d_r));
     HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, nullptr, p->d_r, p->d_z,
                                p->d_rhs2));
     HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z, p->d_x,
