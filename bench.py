@@ -15,6 +15,7 @@ library's stream), and the FP64 oracle timed on the host's cores on a
 bounded sample of subsets, extrapolated by n^3 share.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +31,42 @@ if ROOT not in sys.path:
 METRIC = "s per θ-eval @5M pts, CV loss ≤1e-6 rel vs FP64; kriging p99 latency"
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
+
+
+def measured_traffic(kernel_src, prec):
+    """HBM bytes per launch of the factorisation kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel's
+    source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_potrf_large_5M_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        with open(kernel_src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    entry = t.get(prec)
+    if not entry or t.get("source_sha256") != sha:
+        return None
+    return entry["fetch_bytes"] + entry["write_bytes"]
+
+
+def copy_probe(torch, mib):
+    """A plain device copy of known size (y = 1.0 * x, fp32), for calibrating
+    HBM byte counters; returns the measured copy bandwidth in GB/s."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    torch.mul(x, 1.0, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return gbs
 
 
 def _oracle_subset(args):
@@ -84,6 +121,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 5M workload (testing)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -117,6 +156,7 @@ def main():
     act = mV > 0
     log(f"workload generated in {time.perf_counter() - t0:.1f}s: N={len(w.y)} S={pt.n_subsets} "
         f"train {nT.min()}..{nT.max()} val {mV.min()}..{mV.max()}")
+    copy_gbs = copy_probe(torch, a.copy_probe_mib) if a.copy_probe_mib > 0 else None
     th_true = w.theta_true
     th = pcv.theta(th_true[0], th_true[1], cov=w.cov)
     flops_potrf = float(np.sum(nT[act].astype(np.float64) ** 3 / 3.0 + nT[act] ** 2 / 2.0 + nT[act] / 6.0))
@@ -156,10 +196,13 @@ def main():
     }
     peak = PEAK_FP32_MFMA if a.prec == "mixed" else PEAK_FP64_MFMA
     ach = flops_potrf / (ms_fac * 1e-3) / 1e12
+    src = os.path.join(ROOT, "paper_1912_13132_amd", "csrc", "pcv_potrf.hip")
     out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                       "frac": ach / peak, "traffic": None,
+                       "frac": ach / peak, "traffic": measured_traffic(src, a.prec),
                        "kernel": "k_potrf<float>" if a.prec == "mixed" else "k_potrf<double>",
                        "kernel_ms": ms_fac, "flops_per_launch": flops_potrf}
+    if copy_gbs is not None:
+        out["copy_probe"] = {"mib": a.copy_probe_mib, "GB_per_s": copy_gbs}
     out["loss"] = loss
     out["phase_ms"] = {k: rep[k] for k in ("ms_factor", "ms_solve", "ms_refine", "ms_predict", "ms_reduce")}
     out["max_rel_residual"] = rep["max_rel_residual"]

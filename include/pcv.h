@@ -80,7 +80,8 @@ typedef struct {
 typedef struct {
   int32_t prec;           /* pcv_prec; default PCV_PREC_MIXED                        */
   int32_t max_refine;     /* mixed: refinement sweeps (default 1, max 8)             */
-  double refine_tol;      /* mixed: stop when ||r||_2 <= tol * ||y_T||_2 (1e-12)     */
+  double refine_tol;      /* mixed: a subset whose residual before the last correction
+                             has ||r||_2 > tol * ||y_T||_2 is re-run in FP64 (1e-4)  */
   void* hip_stream;       /* hipStream_t to run on; NULL = library-owned stream      */
   size_t mem_cap_bytes;   /* device workspace cap, 0 = no cap                         */
   int32_t profile;        /* nonzero: time each kernel phase with HIP events          */

@@ -61,7 +61,7 @@ void pcv_default_options(pcv_options* opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->prec = PCV_PREC_MIXED;
   opt->max_refine = 1;
-  opt->refine_tol = 1e-12;
+  opt->refine_tol = 1e-4;
 }
 
 const char* pcv_status_string(pcv_status s) {

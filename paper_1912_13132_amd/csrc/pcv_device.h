@@ -7,12 +7,14 @@
 namespace pcv {
 
 // Tile / block size of the blocked factorisation and of the solves.  Every
-// subset is padded to a multiple of TB with identity rows (covariance 1 on
-// the diagonal, 0 elsewhere, right-hand side 0), which leaves the real
-// part of every result unchanged.
+// subset is padded to a multiple of TB with points at +infinity: their
+// covariance with everything is exactly 0, the factorisation gives them a
+// unit diagonal, their right-hand side is 0, so the real part of every
+// result is unchanged.
 constexpr int TB = 64;
-// Rows of one panel chunk in the factorisation: 4 waves x 64 rows.
-constexpr int CHUNK = 256;
+// Subset status codes: 0 = fine, k > 0 = pivot k-1 not positive,
+// PCV_STATUS_STAGNATED = mixed-precision refinement did not converge.
+constexpr int32_t PCV_STATUS_STAGNATED = -1;
 
 // Per-subset descriptor.  Offsets are element offsets into the packed
 // device arrays.
@@ -105,7 +107,11 @@ hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* t
                         const double* L64, const double* Inv, const double* alpha, const double* qx,
                         const double* qy, const int32_t* qorig, double* Wscratch, double* mean,
                         double* var, int32_t want_var, int32_t obs_noise);
+// Per-subset SSPE and the global loss (fixed-order compensated sums), count
+// of subsets with nonzero status.  With rhs2 non-null, an active subset with
+// rhs2[i] > tol^2 * ynorm2[i] gets status PCV_STATUS_STAGNATED first.
 hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, const double* err,
-                         const int32_t* status, const int32_t* active, double* per_subset_sspe,
+                         int32_t* status, const int32_t* active, const double* rhs2,
+                         const double* ynorm2, double tol, double* per_subset_sspe,
                          double* out_total, int32_t* out_nbad);
 }  // namespace pcv

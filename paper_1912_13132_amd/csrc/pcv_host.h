@@ -42,7 +42,7 @@ struct pcv_problem {
   double *d_rrow = nullptr, *d_pcol = nullptr;
   int64_t nPC = 0;
   int2* d_val_items = nullptr;
-  double *d_tx = nullptr, *d_ty = nullptr, *d_yT = nullptr;
+  double *d_tx = nullptr, *d_ty = nullptr, *d_yT = nullptr, *d_ynorm2 = nullptr;
   // factorisation coordinates, padded to npad per subset with +inf (offP)
   double *d_px64 = nullptr, *d_py64 = nullptr;
   float *d_px32 = nullptr, *d_py32 = nullptr;

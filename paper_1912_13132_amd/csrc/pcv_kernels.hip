@@ -444,8 +444,10 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 
 __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ desc, int S,
                                                 const double* __restrict__ err,
-                                                const int32_t* __restrict__ status,
+                                                int32_t* __restrict__ status,
                                                 const int32_t* __restrict__ active,
+                                                const double* __restrict__ rhs2,
+                                                const double* __restrict__ ynorm2, double tol2,
                                                 double* __restrict__ per_subset,
                                                 double* __restrict__ out_total,
                                                 int32_t* __restrict__ out_nbad) {
@@ -464,6 +466,9 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
         zi = s;
         zc += e;
       }
+      // a mixed-precision subset whose residual before the last correction
+      // was not small enough is re-run in FP64 like a broken-down one
+      if (rhs2 && status[i] == 0 && rhs2[i] > tol2 * ynorm2[i]) status[i] = PCV_STATUS_STAGNATED;
       if (status[i]) ++bad;
     }
     const double z = zi + zc;
@@ -560,10 +565,11 @@ hipError_t launch_predict_val(const Launch& Lc, const int2* items, int n_items, 
 }
 
 hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, const double* err,
-                         const int32_t* status, const int32_t* active, double* per_subset,
-                         double* out_total, int32_t* out_nbad) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, desc, S, err, status, active, per_subset,
-                     out_total, out_nbad);
+                         int32_t* status, const int32_t* active, const double* rhs2,
+                         const double* ynorm2, double tol, double* per_subset, double* out_total,
+                         int32_t* out_nbad) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, desc, S, err, status, active, rhs2, ynorm2,
+                     tol * tol, per_subset, out_total, out_nbad);
   return hipGetLastError();
 }
 

@@ -299,6 +299,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(upload(p, &p->d_vx, vx));
   TRY(upload(p, &p->d_vy, vy));
   TRY(upload(p, &p->d_yV, yV));
+  TRY(upload(p, &p->d_ynorm2, p->ynorm2));
   TRY(dalloc(p, &p->d_z, (size_t)p->nP));
   TRY(dalloc(p, &p->d_x, (size_t)p->nP));
   TRY(dalloc(p, &p->d_alpha, (size_t)p->nP));
@@ -402,8 +403,9 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx, p->d_vy,
                             p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
   if (ev) HIPCHK(hipEventRecord(p->ev[4], p->stream));
-  HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, p->d_sspe, p->d_total,
-                       p->d_nbad));
+  HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active,
+                       sweeps > 0 ? p->d_rhs2 : nullptr, p->d_ynorm2, p->opt.refine_tol, p->d_sspe,
+                       p->d_total, p->d_nbad));
   if (ev) HIPCHK(hipEventRecord(p->ev[5], p->stream));
   HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
@@ -433,8 +435,8 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     if (s == PCV_OK) {
       HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
                                 p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
-      HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, p->d_sspe,
-                           p->d_total, p->d_nbad));
+      HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, nullptr,
+                           nullptr, 0.0, p->d_sspe, p->d_total, p->d_nbad));
       HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));

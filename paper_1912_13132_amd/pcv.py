@@ -123,7 +123,7 @@ class Problem:
     steps 2-5: divide and read once, evaluate many zeta)."""
 
     def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
-                 prec="mixed", max_refine=1, refine_tol=1e-12, stream=None, mem_cap=0,
+                 prec="mixed", max_refine=1, refine_tol=1e-4, stream=None, mem_cap=0,
                  profile=False, debug_flags=0):
         L = lib()
         self._locs = _as(locs, np.float64).reshape(-1, 2)

@@ -181,6 +181,24 @@ def test_mixed_fallback_path(w_plain):
     assert loss == ref
 
 
+def test_refinement_convergence_test_falls_back(w_plain):
+    """refine_tol = 0 fails the per-subset convergence test everywhere, so
+    every subset is re-run in FP64: identical to the FP64 path.  With the
+    default threshold no subset of this well-conditioned problem falls back."""
+    th = pcv.theta(0.1, 0.05)
+    say("[case] refinement convergence test -> fp64 fallback")
+    with pcv.Problem.from_workload(w_plain, prec="mixed", refine_tol=0.0) as P:
+        loss, rep = P.eval(th, report=True)
+    with pcv.Problem.from_workload(w_plain, prec="fp64") as P:
+        ref = P.eval(th)
+    assert rep["n_fallback_fp64"] == rep["n_subsets_used"] == w_plain.part.n_subsets
+    assert loss == ref
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        loss, rep = P.eval(th, report=True)
+    assert rep["n_fallback_fp64"] == 0
+    assert 0.0 < rep["max_rel_residual"] <= 1e-4
+
+
 def test_repeatable_bitwise(w_batched_small):
     """Two evaluations of the same theta are bitwise equal (fixed-order sums)."""
     th = pcv.theta(0.05, 0.1)
