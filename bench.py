@@ -69,6 +69,79 @@ def copy_probe(torch, mib):
     return gbs
 
 
+def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=True, log=print):
+    """Kriging service on the factored problem: Poisson arrivals at `rate`
+    requests/s for `seconds`, each with floor(10^U(0,4)) query locations
+    uniform over the domain (gaps included), plus `n_opt` closed-loop
+    optimisers each walking its own Latin-hypercube design of `n_lhs` points
+    over [theta/2, 2 theta] x [lambda/2, 2 lambda] through the same server."""
+    import threading
+    import queue
+    th0, lam0 = w.theta_true
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 5, seed]))
+    lo, hi = w.locs.min(0), w.locs.max(0)
+    P = pcv.Problem.from_workload(w, prec="mixed")
+    P.factor(pcv.theta(th0, lam0, cov=w.cov))
+    srv = pcv.Server(P, max_inflight=256)
+    stop = threading.Event()
+    evals = []
+
+    def optimiser(k):
+        rr = np.random.default_rng(np.random.SeedSequence([1912, 13132, 5, seed, 100 + k]))
+        u = (rr.permuted(np.tile(np.arange(n_lhs), (2, 1)), axis=1).T + rr.uniform(size=(n_lhs, 2))) / n_lhs
+        for a, b in u:
+            if stop.is_set():
+                return
+            t = pcv.theta(th0 * 4.0 ** (a - 0.5), lam0 * 4.0 ** (b - 0.5), cov=w.cov)
+            evals.append(srv.wait(srv.submit_eval(t)))
+
+    tickets = queue.Queue()
+
+    def collector():
+        while True:
+            t = tickets.get()
+            if t is None:
+                return
+            srv.wait(t)
+
+    col = threading.Thread(target=collector)
+    col.start()
+    opts = [threading.Thread(target=optimiser, args=(k,)) for k in range(n_opt if with_evals else 0)]
+    for t in opts:
+        t.start()
+    t0 = time.perf_counter()
+    t_next = t0
+    n_req = 0
+    while True:
+        t_next += r.exponential(1.0 / rate)
+        if t_next - t0 > seconds:
+            break
+        nq = int(np.floor(10 ** r.uniform(0, 4)))
+        q = r.uniform(lo, hi, (nq, 2))
+        d = t_next - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tickets.put(srv.submit_predict(q, want_var=True))
+        n_req += 1
+    stop.set()
+    tickets.put(None)
+    col.join()
+    for t in opts:
+        t.join()
+    rep = srv.report()
+    srv.close()
+    P.close()
+    out = {"requests": rep["n_predict"], "queries": rep["n_queries"],
+           "p50_ms": 1e3 * rep["p50_s"], "p99_ms": 1e3 * rep["p99_s"], "max_ms": 1e3 * rep["max_s"],
+           "qps": rep["qps"], "evals": rep["n_eval"], "evals_per_s": rep["evals_per_s"],
+           "eval_p50_ms": 1e3 * rep["eval_p50_s"], "eval_p99_ms": 1e3 * rep["eval_p99_s"],
+           "batches": rep["n_batches"], "mean_batch_queries": rep["mean_batch_queries"],
+           "admission_waits": rep["admission_waits"], "workspace_bytes": rep["workspace_bytes"],
+           "seconds": seconds, "rate_req_per_s": rate, "optimisers": len(opts)}
+    log(f"[serve] {'with' if with_evals else 'without'} evaluations: {out}")
+    return out
+
+
 def _oracle_subset(args):
     """CPU-baseline worker: one subset through the FP64 oracle, one BLAS thread."""
     from threadpoolctl import threadpool_limits
@@ -121,6 +194,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 5M workload (testing)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of each serving run (0 = skip serving)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     a = ap.parse_args()
@@ -213,6 +288,11 @@ def main():
                             "factor_frac_fp64_peak": flops_potrf / (ms64 * 1e-3) / 1e12 / PEAK_FP64_MFMA}
         out["rel_err_vs_fp64"] = abs(loss - loss64) / abs(loss64)
         out["speedup_vs_fp64_path"] = s64 / s_per
+    if a.serve_seconds > 0:
+        out["serving"] = {
+            "with_4_optimisers": serve(pcv, w, a.serve_seconds, log=log),
+            "kriging_only": serve(pcv, w, a.serve_seconds, with_evals=False, log=log),
+        }
     if not a.no_cpu:
         cb, rel = cpu_baseline(w, th_true, rep["per_subset_sspe"])
         out["cpu_baseline"] = cb

@@ -176,6 +176,81 @@ pcv_status pcv_problem_info(const pcv_problem* p, int32_t* S, int64_t* nnz_train
 const char* pcv_status_string(pcv_status s);
 const char* pcv_last_error(void);
 
+/* ------------------------------------------------------------ serving --
+ * A server owns a resident problem while it exists (do not call the
+ * pcv_problem functions on it meanwhile) and accepts, from any number of
+ * threads, kriging requests (from the factors of the last pcv_factor, as in
+ * pcv_predict) and theta-evaluation requests (as in pcv_eval), so that the
+ * factored subsets stay in device memory between requests (the data are read
+ * once and evaluated for many zeta, Algorithm 1).
+ *
+ * Continuous batching: kriging requests are routed in the submitting thread
+ * and queued; a batcher packs queued queries, first come first served and
+ * grouped by subset across requests, into the next free workspace slot and
+ * launches it while earlier batches are still on the device; a request
+ * larger than a slot spans several batches.  Evaluations run concurrently
+ * on their own stream.  Each query's result is independent of the batch it
+ * shares (the same bits as pcv_predict).
+ *
+ * Memory-gated admission: the workspace (mem_budget bytes of device memory,
+ * split over 3 slots, plus the same amount of pinned host memory for the
+ * query and result buffers) bounds the queries and kriging items of one
+ * batch; at most max_inflight requests are admitted and unfinished at any
+ * time, and a submit call blocks until a place is free.
+ *
+ * Pointers passed to a submit call (query locations, outputs) must stay
+ * valid until pcv_server_wait for its ticket has returned. */
+typedef struct pcv_server pcv_server;
+typedef int64_t pcv_ticket;
+
+/* mem_budget: workspace bytes, 0 = 8 GiB.  max_inflight >= 1.
+ * Errors: PCV_ERR_INVALID (budget below one kriging item per slot),
+ * PCV_ERR_OOM, PCV_ERR_DEVICE. */
+pcv_status pcv_server_create(pcv_server** out, pcv_problem* p, size_t mem_budget,
+                             int32_t max_inflight);
+
+/* Queue kriging of q query locations (host float64 [q][2]); mean (host
+ * [q]) and var (host [q], may be NULL) are written before pcv_server_wait
+ * returns PCV_OK for *ticket.  obs_noise as in pcv_predict.
+ * Errors: PCV_ERR_INVALID, PCV_ERR_STATE (no pcv_factor before the server
+ * was created). */
+pcv_status pcv_server_submit_predict(pcv_server* s, int64_t q, const double* qlocs, double* mean,
+                                     double* var, int32_t obs_noise, pcv_ticket* ticket);
+
+/* Queue one theta-evaluation; *loss is written before pcv_server_wait
+ * returns PCV_OK for *ticket. */
+pcv_status pcv_server_submit_eval(pcv_server* s, const pcv_theta* theta, double* loss,
+                                  pcv_ticket* ticket);
+
+/* Wait for a request (timeout_s < 0: no limit) and collect it: returns the
+ * request's own status, after which the ticket is no longer valid.
+ * PCV_ERR_BUSY: not finished within timeout_s (the ticket stays valid).
+ * PCV_ERR_INVALID: unknown or already collected ticket. */
+pcv_status pcv_server_wait(pcv_server* s, pcv_ticket ticket, double timeout_s);
+
+/* Latency of finished kriging requests (submit to results written, nearest-
+ * rank percentiles, seconds), kriging queries and evaluations per second
+ * from the first submit to the last completion. */
+pcv_status pcv_server_stats(pcv_server* s, double* p50_s, double* p99_s, double* qps,
+                            double* evals_per_s);
+
+typedef struct {
+  int64_t n_predict, n_eval, n_queries;  /* finished requests / queries     */
+  int64_t n_batches;                     /* kriging launches                */
+  double mean_batch_queries;
+  double p50_s, p99_s, max_s;            /* kriging request latency          */
+  double eval_p50_s, eval_p99_s;         /* evaluation request latency       */
+  double elapsed_s, qps, evals_per_s;
+  int64_t admission_waits;               /* submits that had to wait         */
+  int64_t workspace_bytes;               /* device bytes of the slots        */
+  int64_t batch_query_cap, batch_item_cap;
+} pcv_server_report;
+pcv_status pcv_server_report_get(pcv_server* s, pcv_server_report* out);
+
+/* Finish every queued request, then stop and free the server.  Tickets not
+ * collected become invalid.  The problem stays usable. */
+pcv_status pcv_server_destroy(pcv_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HIP_SOURCES = ["pcv_potrf.hip", "pcv_kernels.hip", "pcv_krige.hip"]
-CPP_SOURCES = ["pcv_capi.cpp", "pcv_problem.cpp"]
+CPP_SOURCES = ["pcv_capi.cpp", "pcv_problem.cpp", "pcv_server.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]
@@ -56,7 +56,7 @@ def build(verbose=False, jobs=4):
         list(ex.map(lambda c: _run(c, verbose), cmds))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
-         + ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")],
+         + ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lpthread", "-Wl,-rpath," + os.path.join(ROCM, "lib")],
          verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -189,4 +189,64 @@ pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* m
   return pcv::predict_impl(p, q, qlocs, mean, var, obs_noise, owner);
 }
 
+pcv_status pcv_server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight) {
+  pcv::g_err.clear();
+  if (!out) return fail(PCV_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (max_inflight < 1) return fail(PCV_ERR_INVALID, "max_inflight must be >= 1");
+  return pcv::server_create(out, p, mem_budget, max_inflight, 3);
+}
+
+pcv_status pcv_server_submit_predict(pcv_server* s, int64_t q, const double* qlocs, double* mean,
+                                     double* var, int32_t obs_noise, pcv_ticket* ticket) {
+  pcv::g_err.clear();
+  if (!s || !ticket) return fail(PCV_ERR_INVALID, "server or ticket is NULL");
+  if (q < 0 || q > INT32_MAX || (q > 0 && (!qlocs || !mean))) return fail(PCV_ERR_INVALID, "bad query arguments");
+  for (int64_t j = 0; j < 2 * q; ++j)
+    if (!is_finite(qlocs[j])) return fail(PCV_ERR_INVALID, "non-finite query location");
+  if (!pcv::server_problem(s)->factored) return fail(PCV_ERR_STATE, "kriging request before pcv_factor");
+  return pcv::server_submit_predict(s, q, qlocs, mean, var, obs_noise, ticket);
+}
+
+pcv_status pcv_server_submit_eval(pcv_server* s, const pcv_theta* theta, double* loss, pcv_ticket* ticket) {
+  pcv::g_err.clear();
+  if (!s || !ticket || !loss) return fail(PCV_ERR_INVALID, "server, loss or ticket is NULL");
+  pcv_status st = check_theta(theta);
+  if (st != PCV_OK) return st;
+  return pcv::server_submit_eval(s, *theta, loss, ticket);
+}
+
+pcv_status pcv_server_wait(pcv_server* s, pcv_ticket ticket, double timeout_s) {
+  pcv::g_err.clear();
+  if (!s) return fail(PCV_ERR_INVALID, "server is NULL");
+  if (std::isnan(timeout_s)) return fail(PCV_ERR_INVALID, "timeout is NaN");
+  return pcv::server_wait(s, ticket, timeout_s);
+}
+
+pcv_status pcv_server_stats(pcv_server* s, double* p50_s, double* p99_s, double* qps, double* evals_per_s) {
+  pcv::g_err.clear();
+  if (!s) return fail(PCV_ERR_INVALID, "server is NULL");
+  pcv_server_report r;
+  pcv_status st = pcv::server_report(s, &r);
+  if (st != PCV_OK) return st;
+  if (p50_s) *p50_s = r.p50_s;
+  if (p99_s) *p99_s = r.p99_s;
+  if (qps) *qps = r.qps;
+  if (evals_per_s) *evals_per_s = r.evals_per_s;
+  return PCV_OK;
+}
+
+pcv_status pcv_server_report_get(pcv_server* s, pcv_server_report* out) {
+  pcv::g_err.clear();
+  if (!s || !out) return fail(PCV_ERR_INVALID, "server or report is NULL");
+  return pcv::server_report(s, out);
+}
+
+pcv_status pcv_server_destroy(pcv_server* s) {
+  pcv::g_err.clear();
+  if (!s) return fail(PCV_ERR_INVALID, "server is NULL");
+  return pcv::server_destroy(s);
+}
+
 }  // extern "C"

@@ -95,18 +95,24 @@ hipError_t launch_predict_val(const Launch& L, const int2* items, int n_items, c
                               const double* ty, const double* vx, const double* vy,
                               const double* yV, const double* alpha, double* yhat, double* err);
 // Kriging of query points from resident FP64 factors (mean and variance).
+constexpr int KRIGE_Q = 16;  // queries per kriging item
 struct KrigeItem {
   int32_t sidx;    // subset
   int32_t q0;      // first query (in the grouped query arrays)
-  int32_t nq;      // queries in this item (<= 64)
-  int32_t pad;
-  int64_t woff;    // scratch offset (npad x 64 doubles)
+  int32_t nq;      // queries in this item (<= KRIGE_Q)
+  int32_t flags;   // KRIGE_VAR: some query of the item wants its variance
+  int64_t woff;    // scratch offset (npad x KRIGE_Q doubles), used with KRIGE_VAR
 };
+// Per-query flags (and KRIGE_VAR per item).
+constexpr int32_t KRIGE_VAR = 1;        // write the kriging variance
+constexpr int32_t KRIGE_OBS_NOISE = 2;  // add the nugget variance sigma^2 lambda
+// Grouped query j (centred coordinates qx/qy[j], flags qflag[j]) writes
+// mean[qorig[j]] and, with KRIGE_VAR, var[qorig[j]].
 hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* theta,
                         const KrigeItem* items, int n_items, const double* tx, const double* ty,
                         const double* L64, const double* Inv, const double* alpha, const double* qx,
-                        const double* qy, const int32_t* qorig, double* Wscratch, double* mean,
-                        double* var, int32_t want_var, int32_t obs_noise);
+                        const double* qy, const int32_t* qorig, const int32_t* qflag,
+                        double* Wscratch, double* mean, double* var);
 // Per-subset SSPE and the global loss (fixed-order compensated sums), count
 // of subsets with nonzero status.  With rhs2 non-null, an active subset with
 // rhs2[i] > tol^2 * ynorm2[i] gets status PCV_STATUS_STAGNATED first.

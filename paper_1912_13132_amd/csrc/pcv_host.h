@@ -9,6 +9,14 @@
 #include "../../include/pcv.h"
 #include "pcv_device.h"
 
+// Bucket grid over the core rectangles for routing query locations
+// (built once per problem when core rectangles are given).
+struct pcv_router {
+  int G = 0;
+  double xmin = 0, ymin = 0, xmax = 0, ymax = 0, bw = 0, bh = 0;
+  std::vector<int32_t> ptr, list;  // CSR: cores touching bucket b
+};
+
 struct pcv_problem {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -25,6 +33,7 @@ struct pcv_problem {
   std::vector<int2> tile_items;     // (subset, row block I), by decreasing I (residual tiles)
   std::vector<int2> val_items;      // (subset, 64-point validation block)
   std::vector<double> core_rect;    // S x 4, empty when not given
+  pcv_router router;
   std::vector<double> centroid;     // S x 2
   std::vector<double> ynorm2;       // S: ||y_T||^2
   int64_t nnzT = 0, nnzV = 0, nP = 0, nL = 0, nInv = 0, n_val_total = 0;
@@ -92,4 +101,32 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
 pcv_status factor_impl(pcv_problem* p, const pcv_theta& th);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
                         int32_t obs_noise, int32_t* owner);
+pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,
+                         int32_t n_slots);
+pcv_status server_submit_predict(pcv_server* s, int64_t q, const double* ql, double* mean, double* var,
+                                 int32_t obs_noise, pcv_ticket* ticket);
+pcv_status server_submit_eval(pcv_server* s, const pcv_theta& th, double* loss, pcv_ticket* ticket);
+pcv_status server_wait(pcv_server* s, pcv_ticket t, double timeout_s);
+pcv_status server_report(pcv_server* s, pcv_server_report* out);
+pcv_status server_destroy(pcv_server* s);
+const pcv_problem* server_problem(const pcv_server* s);
+
+// Owning subset of each query location (half-open cores, nearest core
+// outside all of them; nearest training centroid without core rectangles).
+void route(const pcv_problem* p, int64_t q, const double* ql, int32_t* owner);
+
+// Host plan of one kriging launch: queries grouped by owning subset, in
+// 64-query items.  Input j of the plan is query j of the caller's list.
+struct KrigePlan {
+  std::vector<double> qx, qy;      // grouped, centred on the subset centroid
+  std::vector<int32_t> qorig;      // grouped -> input index
+  std::vector<int32_t> qflag;      // grouped flags (KRIGE_VAR | KRIGE_OBS_NOISE)
+  std::vector<KrigeItem> items;
+  int64_t w_doubles = 0;           // variance scratch
+  std::vector<int32_t> cnt, pos;   // counting-sort work arrays (size S)
+};
+// owner[j] is the subset of query j; flags[j] its flags (or `flag_all` when
+// flags is null).  Items get scratch only when they need the variance.
+void plan_krige(const pcv_problem* p, int64_t q, const double* ql, const int32_t* owner,
+                const int32_t* flags, int32_t flag_all, KrigePlan& plan);
 }  // namespace pcv

@@ -91,47 +91,70 @@ std::vector<int32_t> lpt_order(const std::vector<SubsetDesc>& d, const std::vect
   return o;
 }
 
-// Route queries to cores: half-open [lo, hi) per axis, edges on the domain
-// maximum closed, lowest index first; a point in no core goes to the
-// nearest core rectangle.  Without rectangles: nearest training centroid.
-void route(const pcv_problem* p, int64_t q, const double* ql, std::vector<int32_t>& owner) {
-  owner.assign(q, 0);
+// Bucket grid over the core rectangles: G x G buckets spanning the domain,
+// each listing the cores that touch it.
+void build_router(pcv_problem* p) {
   const int S = p->S;
-  if (!p->core_rect.empty()) {
-    const double* R = p->core_rect.data();
-    double xmax = -INFINITY, ymax = -INFINITY, xmin = INFINITY, ymin = INFINITY;
+  pcv_router& R = p->router;
+  const double* C = p->core_rect.data();
+  R.xmax = R.ymax = -INFINITY;
+  R.xmin = R.ymin = INFINITY;
+  for (int i = 0; i < S; ++i) {
+    R.xmin = std::min(R.xmin, C[4 * i + 0]);
+    R.ymin = std::min(R.ymin, C[4 * i + 1]);
+    R.xmax = std::max(R.xmax, C[4 * i + 2]);
+    R.ymax = std::max(R.ymax, C[4 * i + 3]);
+  }
+  R.G = std::max(1, std::min(512, (int)std::sqrt((double)S) * 2));
+  R.bw = (R.xmax - R.xmin) / R.G;
+  R.bh = (R.ymax - R.ymin) / R.G;
+  const int G = R.G;
+  auto bx = [&](double x) { return std::min(G - 1, std::max(0, (int)std::floor((x - R.xmin) / R.bw))); };
+  auto by = [&](double y) { return std::min(G - 1, std::max(0, (int)std::floor((y - R.ymin) / R.bh))); };
+  std::vector<std::vector<int32_t>> buckets((size_t)G * G);
+  if (R.bw > 0 && R.bh > 0)
     for (int i = 0; i < S; ++i) {
-      xmax = std::max(xmax, R[4 * i + 2]);
-      ymax = std::max(ymax, R[4 * i + 3]);
-      xmin = std::min(xmin, R[4 * i + 0]);
-      ymin = std::min(ymin, R[4 * i + 1]);
-    }
-    // uniform bucket grid over the domain listing the cores that touch each bucket
-    const int G = std::max(1, std::min(512, (int)std::sqrt((double)S) * 2));
-    const double bw = (xmax - xmin) / G, bh = (ymax - ymin) / G;
-    std::vector<std::vector<int32_t>> buckets((size_t)G * G);
-    auto bx = [&](double x) { return std::min(G - 1, std::max(0, (int)std::floor((x - xmin) / bw))); };
-    auto by = [&](double y) { return std::min(G - 1, std::max(0, (int)std::floor((y - ymin) / bh))); };
-    for (int i = 0; i < S; ++i) {
-      const int x0 = bx(R[4 * i]), x1 = bx(R[4 * i + 2]), y0 = by(R[4 * i + 1]), y1 = by(R[4 * i + 3]);
+      const int x0 = bx(C[4 * i]), x1 = bx(C[4 * i + 2]), y0 = by(C[4 * i + 1]), y1 = by(C[4 * i + 3]);
       for (int yy = y0; yy <= y1; ++yy)
         for (int xx = x0; xx <= x1; ++xx) buckets[(size_t)yy * G + xx].push_back(i);
     }
+  R.ptr.assign((size_t)G * G + 1, 0);
+  for (size_t b = 0; b < buckets.size(); ++b) R.ptr[b + 1] = R.ptr[b] + (int32_t)buckets[b].size();
+  R.list.clear();
+  for (auto& v : buckets) R.list.insert(R.list.end(), v.begin(), v.end());
+}
+
+}  // namespace
+
+// Route queries to cores: half-open [lo, hi) per axis, edges on the domain
+// maximum closed, lowest index first; a point in no core goes to the
+// nearest core rectangle (lowest index on ties).  Without rectangles: the
+// nearest training centroid.
+void route(const pcv_problem* p, int64_t q, const double* ql, int32_t* owner) {
+  const int S = p->S;
+  if (!p->core_rect.empty()) {
+    const double* C = p->core_rect.data();
+    const pcv_router& R = p->router;
+    const int G = R.G;
     for (int64_t j = 0; j < q; ++j) {
       const double x = ql[2 * j], y = ql[2 * j + 1];
       int hit = -1;
-      if (x >= xmin && x <= xmax && y >= ymin && y <= ymax && bw > 0 && bh > 0) {
-        for (int32_t i : buckets[(size_t)by(y) * G + bx(x)]) {
-          const double* r = R + 4 * i;
-          const bool inx = x >= r[0] && (x < r[2] || (x == r[2] && r[2] == xmax));
-          const bool iny = y >= r[1] && (y < r[3] || (y == r[3] && r[3] == ymax));
+      if (x >= R.xmin && x <= R.xmax && y >= R.ymin && y <= R.ymax && R.bw > 0 && R.bh > 0) {
+        const int bxi = std::min(G - 1, std::max(0, (int)std::floor((x - R.xmin) / R.bw)));
+        const int byi = std::min(G - 1, std::max(0, (int)std::floor((y - R.ymin) / R.bh)));
+        const size_t b = (size_t)byi * G + bxi;
+        for (int32_t k = R.ptr[b]; k < R.ptr[b + 1]; ++k) {
+          const int32_t i = R.list[k];
+          const double* r = C + 4 * i;
+          const bool inx = x >= r[0] && (x < r[2] || (x == r[2] && r[2] == R.xmax));
+          const bool iny = y >= r[1] && (y < r[3] || (y == r[3] && r[3] == R.ymax));
           if (inx && iny && (hit < 0 || i < hit)) hit = i;
         }
       }
       if (hit < 0) {
         double best = INFINITY;
         for (int i = 0; i < S; ++i) {
-          const double* r = R + 4 * i;
+          const double* r = C + 4 * i;
           const double dx = std::max(std::max(r[0] - x, 0.0), x - r[2]);
           const double dy = std::max(std::max(r[1] - y, 0.0), y - r[3]);
           const double d2 = dx * dx + dy * dy;
@@ -161,7 +184,44 @@ void route(const pcv_problem* p, int64_t q, const double* ql, std::vector<int32_
   }
 }
 
-}  // namespace
+void plan_krige(const pcv_problem* p, int64_t q, const double* ql, const int32_t* owner,
+                const int32_t* flags, int32_t flag_all, KrigePlan& P) {
+  const int S = p->S;
+  P.qx.resize(q);
+  P.qy.resize(q);
+  P.qorig.resize(q);
+  P.qflag.resize(q);
+  P.items.clear();
+  P.w_doubles = 0;
+  // counting sort by owner keeps the input order inside a subset
+  P.cnt.assign(S + 1, 0);
+  for (int64_t j = 0; j < q; ++j) ++P.cnt[owner[j] + 1];
+  for (int i = 0; i < S; ++i) P.cnt[i + 1] += P.cnt[i];
+  P.pos.assign(P.cnt.begin(), P.cnt.end() - 1);
+  for (int64_t j = 0; j < q; ++j) {
+    const int32_t i = owner[j];
+    const int64_t k = P.pos[i]++;
+    P.qx[k] = ql[2 * j] - p->centroid[2 * i];
+    P.qy[k] = ql[2 * j + 1] - p->centroid[2 * i + 1];
+    P.qorig[k] = (int32_t)j;
+    P.qflag[k] = flags ? flags[j] : flag_all;
+  }
+  for (int i = 0; i < S; ++i)
+    for (int64_t k = P.cnt[i]; k < P.cnt[i + 1]; k += KRIGE_Q) {
+      KrigeItem it;
+      it.sidx = i;
+      it.q0 = (int32_t)k;
+      it.nq = (int32_t)std::min<int64_t>(KRIGE_Q, P.cnt[i + 1] - k);
+      it.flags = 0;
+      for (int64_t m = k; m < k + it.nq; ++m) it.flags |= P.qflag[m] & KRIGE_VAR;
+      it.woff = 0;
+      if (it.flags & KRIGE_VAR) {
+        it.woff = P.w_doubles;
+        P.w_doubles += (int64_t)p->desc[i].npad * KRIGE_Q;
+      }
+      P.items.push_back(it);
+    }
+}
 
 pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const double* y, int32_t S,
                          const int64_t* tptr, const int32_t* tidx, const int64_t* vptr,
@@ -180,7 +240,10 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   p->active.assign(S, 0);
   p->centroid.assign(2 * (size_t)S, 0.0);
   p->ynorm2.assign(S, 0.0);
-  if (core_rect) p->core_rect.assign(core_rect, core_rect + 4 * (size_t)S);
+  if (core_rect) {
+    p->core_rect.assign(core_rect, core_rect + 4 * (size_t)S);
+    build_router(p);
+  }
 
   int64_t offT = 0, offV = 0, offP = 0, offL = 0, offInv = 0, offPC = 0;
   std::vector<int32_t> act_ids, all_ids;
@@ -532,75 +595,43 @@ pcv_status predict_impl(pcv_problem* p, int64_t q, const double* ql, double* mea
                         int32_t obs_noise, int32_t* owner_out) {
   HIPCHK(hipSetDevice(p->device));
   if (q == 0) return PCV_OK;
-  std::vector<int32_t> owner;
-  route(p, q, ql, owner);
+  std::vector<int32_t> owner(q);
+  route(p, q, ql, owner.data());
   if (owner_out) std::copy(owner.begin(), owner.end(), owner_out);
-  // group queries by subset
-  std::vector<int64_t> perm(q);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return owner[a] < owner[b]; });
-  std::vector<double> qx(q), qy(q);
-  std::vector<int32_t> qorig(q);
-  std::vector<KrigeItem> items;
-  int64_t woff = 0;
-  for (int64_t k = 0; k < q;) {
-    const int32_t i = owner[perm[k]];
-    int64_t e = k;
-    while (e < q && owner[perm[e]] == i) ++e;
-    for (int64_t j = k; j < e; ++j) {
-      qx[j] = ql[2 * perm[j]] - p->centroid[2 * i];
-      qy[j] = ql[2 * perm[j] + 1] - p->centroid[2 * i + 1];
-      qorig[j] = (int32_t)perm[j];
-    }
-    for (int64_t j = k; j < e; j += 64) {
-      KrigeItem it;
-      it.sidx = i;
-      it.q0 = (int32_t)j;
-      it.nq = (int32_t)std::min<int64_t>(64, e - j);
-      it.pad = 0;
-      it.woff = woff;
-      woff += (int64_t)p->desc[i].npad * 64;
-      items.push_back(it);
-    }
-    k = e;
-  }
+  KrigePlan P;
+  const int32_t flag = (var ? KRIGE_VAR : 0) | (obs_noise ? KRIGE_OBS_NOISE : 0);
+  plan_krige(p, q, ql, owner.data(), nullptr, flag, P);
   // transient device buffers for this request
   double *d_qx = nullptr, *d_qy = nullptr, *d_mean = nullptr, *d_var = nullptr, *d_W = nullptr;
-  int32_t* d_qorig = nullptr;
+  int32_t *d_qorig = nullptr, *d_qflag = nullptr;
   KrigeItem* d_items = nullptr;
-  auto cleanup = [&]() {
-    (void)hipFree(d_qx);
-    (void)hipFree(d_qy);
-    (void)hipFree(d_mean);
-    (void)hipFree(d_var);
-    (void)hipFree(d_W);
-    (void)hipFree(d_qorig);
-    (void)hipFree(d_items);
-  };
+  const size_t ni = P.items.size();
   hipError_t e = hipSuccess;
-  const bool want_var = var != nullptr;
   if (e == hipSuccess) e = hipMalloc((void**)&d_qx, sizeof(double) * q);
   if (e == hipSuccess) e = hipMalloc((void**)&d_qy, sizeof(double) * q);
   if (e == hipSuccess) e = hipMalloc((void**)&d_mean, sizeof(double) * q);
   if (e == hipSuccess) e = hipMalloc((void**)&d_var, sizeof(double) * q);
   if (e == hipSuccess) e = hipMalloc((void**)&d_qorig, sizeof(int32_t) * q);
-  if (e == hipSuccess) e = hipMalloc((void**)&d_items, sizeof(KrigeItem) * items.size());
-  if (e == hipSuccess && want_var) e = hipMalloc((void**)&d_W, sizeof(double) * std::max<int64_t>(woff, 1));
-  if (e == hipSuccess) e = hipMemcpyAsync(d_qx, qx.data(), sizeof(double) * q, hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_qy, qy.data(), sizeof(double) * q, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_qflag, sizeof(int32_t) * q);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_items, sizeof(KrigeItem) * ni);
+  if (e == hipSuccess && P.w_doubles) e = hipMalloc((void**)&d_W, sizeof(double) * P.w_doubles);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_qx, P.qx.data(), sizeof(double) * q, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_qy, P.qy.data(), sizeof(double) * q, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_qorig, qorig.data(), sizeof(int32_t) * q, hipMemcpyHostToDevice, p->stream);
+    e = hipMemcpyAsync(d_qorig, P.qorig.data(), sizeof(int32_t) * q, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_items, items.data(), sizeof(KrigeItem) * items.size(), hipMemcpyHostToDevice, p->stream);
+    e = hipMemcpyAsync(d_qflag, P.qflag.data(), sizeof(int32_t) * q, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess)
-    e = launch_krige(p->stream, p->d_desc, p->d_theta_fact, d_items, (int)items.size(), p->d_tx, p->d_ty,
-                     p->d_Lf, p->d_Invf, p->d_alpha_fact, d_qx, d_qy, d_qorig, d_W, d_mean, d_var, want_var ? 1 : 0,
-                     obs_noise);
+    e = hipMemcpyAsync(d_items, P.items.data(), sizeof(KrigeItem) * ni, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = launch_krige(p->stream, p->d_desc, p->d_theta_fact, d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
+                     p->d_Invf, p->d_alpha_fact, d_qx, d_qy, d_qorig, d_qflag, d_W, d_mean, d_var);
   if (e == hipSuccess) e = hipMemcpyAsync(mean, d_mean, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
-  if (e == hipSuccess && want_var)
-    e = hipMemcpyAsync(var, d_var, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess && var) e = hipMemcpyAsync(var, d_var, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-  cleanup();
+  for (void* b : {(void*)d_qx, (void*)d_qy, (void*)d_mean, (void*)d_var, (void*)d_W, (void*)d_qorig,
+                  (void*)d_qflag, (void*)d_items})
+    (void)hipFree(b);
   if (e != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,
                 std::string("predict: ") + hipGetErrorString(e));

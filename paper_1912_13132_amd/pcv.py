@@ -21,6 +21,7 @@ COV_MATERN32 = 1
 PREC_FP64 = 0
 PREC_MIXED = 1
 MAX_SUBSET = 16384
+KRIGE_Q = 16  # queries per kriging work item (variance scratch npad x KRIGE_Q doubles)
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -57,6 +58,18 @@ class EvalReport(ctypes.Structure):
                 ("per_subset_iters", _c_int32_p)]
 
 
+class ServerReport(ctypes.Structure):
+    _fields_ = [("n_predict", ctypes.c_int64), ("n_eval", ctypes.c_int64),
+                ("n_queries", ctypes.c_int64), ("n_batches", ctypes.c_int64),
+                ("mean_batch_queries", ctypes.c_double),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("max_s", ctypes.c_double),
+                ("eval_p50_s", ctypes.c_double), ("eval_p99_s", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double), ("qps", ctypes.c_double),
+                ("evals_per_s", ctypes.c_double), ("admission_waits", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("batch_query_cap", ctypes.c_int64),
+                ("batch_item_cap", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -82,12 +95,22 @@ def lib():
     L.pcv_problem_destroy.argtypes = [P]
     L.pcv_problem_info.argtypes = [P, _c_int32_p, _c_int64_p, _c_int32_p,
                                    ctypes.POINTER(ctypes.c_size_t)]
+    L.pcv_server_create.argtypes = [ctypes.POINTER(P), P, ctypes.c_size_t, ctypes.c_int32]
+    L.pcv_server_submit_predict.argtypes = [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
+                                            ctypes.c_int32, _c_int64_p]
+    L.pcv_server_submit_eval.argtypes = [P, ctypes.POINTER(Theta), _c_double_p, _c_int64_p]
+    L.pcv_server_wait.argtypes = [P, ctypes.c_int64, ctypes.c_double]
+    L.pcv_server_stats.argtypes = [P, _c_double_p, _c_double_p, _c_double_p, _c_double_p]
+    L.pcv_server_report_get.argtypes = [P, ctypes.POINTER(ServerReport)]
+    L.pcv_server_destroy.argtypes = [P]
     L.pcv_status_string.argtypes = [ctypes.c_int]
     L.pcv_status_string.restype = ctypes.c_char_p
     L.pcv_last_error.argtypes = []
     L.pcv_last_error.restype = ctypes.c_char_p
     for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
-              "pcv_problem_destroy", "pcv_problem_info"):
+              "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create",
+              "pcv_server_submit_predict", "pcv_server_submit_eval", "pcv_server_wait",
+              "pcv_server_stats", "pcv_server_report_get", "pcv_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -220,6 +243,86 @@ class Problem:
         if self._h is not None:
             lib().pcv_problem_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over a factored problem (continuous batching of kriging
+    requests, concurrent theta-evaluations).  The problem must not be used
+    directly while the server exists.  Submit calls may come from several
+    threads; they release the GIL while they block on admission."""
+
+    def __init__(self, problem, mem_budget=0, max_inflight=64):
+        self.problem = problem
+        h = ctypes.c_void_p()
+        _check(lib().pcv_server_create(ctypes.byref(h), problem._handle(), int(mem_budget),
+                                       int(max_inflight)))
+        self._h = h
+        self._keep = {}
+
+    def _handle(self):
+        if self._h is None:
+            raise PcvError(1, "server destroyed")
+        return self._h
+
+    def submit_predict(self, q, want_var=True, obs_noise=False):
+        """Queue kriging at query locations q ([k][2]); returns a ticket."""
+        q = _as(q, np.float64).reshape(-1, 2)
+        nq = q.shape[0]
+        mean = np.zeros(nq)
+        var = np.zeros(nq) if want_var else None
+        t = ctypes.c_int64()
+        _check(lib().pcv_server_submit_predict(
+            self._handle(), nq, _ptr(q, ctypes.c_double), _ptr(mean, ctypes.c_double),
+            None if var is None else _ptr(var, ctypes.c_double), 1 if obs_noise else 0,
+            ctypes.byref(t)))
+        self._keep[t.value] = ("predict", q, mean, var)
+        return t.value
+
+    def submit_eval(self, th):
+        """Queue one theta-evaluation; returns a ticket."""
+        loss = np.zeros(1)
+        t = ctypes.c_int64()
+        _check(lib().pcv_server_submit_eval(self._handle(), ctypes.byref(th),
+                                            _ptr(loss, ctypes.c_double), ctypes.byref(t)))
+        self._keep[t.value] = ("eval", th, loss)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        """(mean, var) of a kriging request or the loss of an evaluation.
+        Raises PcvError with status PCV_ERR_BUSY on timeout."""
+        _check(lib().pcv_server_wait(self._handle(), int(ticket), float(timeout)))
+        k = self._keep.pop(ticket)
+        if k[0] == "predict":
+            return k[2], k[3]
+        return float(k[2][0])
+
+    def stats(self):
+        v = [ctypes.c_double() for _ in range(4)]
+        _check(lib().pcv_server_stats(self._handle(), *[ctypes.byref(x) for x in v]))
+        return dict(p50_s=v[0].value, p99_s=v[1].value, qps=v[2].value, evals_per_s=v[3].value)
+
+    def report(self):
+        r = ServerReport()
+        _check(lib().pcv_server_report_get(self._handle(), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in ServerReport._fields_}
+
+    def close(self):
+        if self._h is not None:
+            lib().pcv_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __enter__(self):
         return self

@@ -85,3 +85,26 @@ def test_status_strings():
     L = pcv.lib()
     assert L.pcv_status_string(0) == b"PCV_OK"
     assert L.pcv_status_string(3) == b"PCV_ERR_NOT_PD"
+
+
+def test_server_calls_reject_null_handles():
+    """The serving calls validate their handles before any device work."""
+    L = pcv.lib()
+    out = ctypes.c_void_p(1)
+    assert L.pcv_server_create(ctypes.byref(out), None, 0, 4) == 1
+    assert out.value is None
+    assert L.pcv_server_create(None, None, 0, 4) == 1
+    t = ctypes.c_int64()
+    q = np.zeros((1, 2))
+    m = np.zeros(1)
+    assert L.pcv_server_submit_predict(None, 1, q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0,
+                                       ctypes.byref(t)) == 1
+    th = pcv.theta(0.1, 0.1)
+    loss = ctypes.c_double()
+    assert L.pcv_server_submit_eval(None, ctypes.byref(th), ctypes.byref(loss), ctypes.byref(t)) == 1
+    assert L.pcv_server_wait(None, 1, 0.0) == 1
+    assert L.pcv_server_stats(None, None, None, None, None) == 1
+    assert L.pcv_server_report_get(None, None) == 1
+    assert L.pcv_server_destroy(None) == 1
+    assert b"NULL" in L.pcv_last_error()
