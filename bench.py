@@ -267,7 +267,8 @@ def main():
                                "covariance range 50 nugget 0.1, 2400 recursive cores, 20% overlap",
                    "n_points": int(len(w.y)), "subsets": int(pt.n_subsets),
                    "train_min": int(nT.min()), "train_max": int(nT.max()),
-                   "n_val": int(rep["n_val"]), "precision": a.prec, "max_refine": a.max_refine},
+                   "n_val": int(rep["n_val"]), "precision": a.prec, "max_refine": a.max_refine,
+                   "launch": "HIP graphs, one per phase, with the phase events recorded between them"},
     }
     peak = PEAK_FP32_MFMA if a.prec == "mixed" else PEAK_FP64_MFMA
     ach = flops_potrf / (ms_fac * 1e-3) / 1e12

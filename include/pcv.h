@@ -88,7 +88,9 @@ typedef struct {
   int32_t debug_flags;    /* testing hook, 0 in production.  Bit 0: in mixed mode
                              treat every FP32 factorisation as broken down, so the
                              FP64 fallback path runs for every subset              */
-  int32_t reserved[6];
+  int32_t graph;          /* nonzero (default): capture the theta-evaluation once as a
+                             HIP graph and replay it; 0: launch kernel by kernel  */
+  int32_t reserved[5];
 } pcv_options;
 
 /* Per-evaluation report.  Arrays are optional, caller-owned, length S. */

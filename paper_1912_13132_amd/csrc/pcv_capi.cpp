@@ -62,6 +62,7 @@ void pcv_default_options(pcv_options* opt) {
   opt->prec = PCV_PREC_MIXED;
   opt->max_refine = 1;
   opt->refine_tol = 1e-4;
+  opt->graph = 1;
 }
 
 const char* pcv_status_string(pcv_status s) {

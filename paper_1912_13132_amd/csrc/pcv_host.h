@@ -60,6 +60,9 @@ struct pcv_problem {
   double *d_yhat = nullptr, *d_err = nullptr;
   double *d_logdet = nullptr, *d_sspe = nullptr;
   int32_t* d_status = nullptr;
+  int32_t* d_bad = nullptr;         // subsets re-run in FP64
+  // captured theta-evaluation: [0] whole, [1 + k] phase k (when profiling)
+  hipGraphExec_t graph_exec[8] = {};
   pcv::ThetaDev* d_theta = nullptr;
   double* d_total = nullptr;
   int32_t* d_nbad = nullptr;

@@ -66,7 +66,8 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-pcv_status set_theta(pcv_problem* p, const pcv_theta& th) {
+// Fill the pinned theta block; the evaluation sequence uploads it.
+void set_theta_host(pcv_problem* p, const pcv_theta& th) {
   ThetaDev* h = p->h_theta;
   h->cov = th.cov;
   h->pad = 0;
@@ -74,8 +75,6 @@ pcv_status set_theta(pcv_problem* p, const pcv_theta& th) {
   h->inv_range = 1.0 / th.range;
   h->lambda = th.lambda;
   h->sigma2 = th.sigma2;
-  HIPCHK(hipMemcpyAsync(p->d_theta, h, sizeof(ThetaDev), hipMemcpyHostToDevice, p->stream));
-  return PCV_OK;
 }
 
 pcv_status ensure_L(pcv_problem* p, bool fp64) {
@@ -375,6 +374,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(dalloc(p, &p->d_logdet, (size_t)S));
   TRY(dalloc(p, &p->d_sspe, (size_t)S));
   TRY(dalloc(p, &p->d_status, (size_t)S));
+  TRY(dalloc(p, &p->d_bad, (size_t)S));
   TRY(dalloc(p, &p->d_theta, 1));
   TRY(dalloc(p, &p->d_total, 1));
   TRY(dalloc(p, &p->d_nbad, 1));
@@ -395,6 +395,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
 void problem_free(pcv_problem* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (auto& g : p->graph_exec)
+    if (g) (void)hipGraphExecDestroy(g);
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
   if (p->h_theta) (void)hipHostFree(p->h_theta);
@@ -422,57 +424,143 @@ pcv_status factor_solve64(pcv_problem* p, const ThetaDev* d_theta, const int32_t
 
 }  // namespace
 
+namespace {
+
+// Phases of one theta-evaluation: upload of the theta block from pinned
+// memory, factorisation, solves, refinement sweeps, kriging of the
+// validation points, reduction, download of the loss and of the count of
+// subsets that need the FP64 re-run.  Profiling records an event after each
+// of the first six.
+constexpr int N_PHASES = 7;
+
+pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, int sweeps) {
+  Launch Lc{st, p->d_desc, p->d_theta};
+  switch (phase) {
+    case 0:
+      HIPCHK(hipMemcpyAsync(p->d_theta, p->h_theta, sizeof(ThetaDev), hipMemcpyHostToDevice, st));
+      break;
+    case 1:
+      if (mixed)
+        HIPCHK(launch_potrf_f32(Lc, p->d_order_eval, p->n_active, p->d_px32, p->d_py32, p->d_L32, p->d_Inv,
+                                p->d_logdet, p->d_status));
+      else
+        HIPCHK(launch_potrf_f64(Lc, p->d_order_eval, p->n_active, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
+                                p->d_logdet, p->d_status));
+      break;
+    case 2:
+      if (mixed) {
+        HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_yT,
+                                   nullptr, p->d_z, nullptr));
+        HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
+                                   p->d_alpha, nullptr));
+      } else {
+        HIPCHK(launch_trsv_fwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_yT,
+                                   nullptr, p->d_z, nullptr));
+        HIPCHK(launch_trsv_bwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_z,
+                                   p->d_alpha, nullptr));
+      }
+      break;
+    case 3:
+      for (int it = 0; it < sweeps; ++it) {
+        HIPCHK(launch_residual(Lc, p->d_tile_items, (int)p->tile_items.size(), p->d_row_items,
+                               (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT, p->d_alpha, p->d_rrow,
+                               p->d_pcol, p->d_r));
+        HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, nullptr,
+                                   p->d_r, p->d_z, p->d_rhs2));
+        HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
+                                   p->d_x, p->d_alpha));
+      }
+      break;
+    case 4:
+      HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
+                                p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
+      break;
+    case 5:
+      HIPCHK(launch_reduce(st, p->d_desc, p->S, p->d_err, p->d_status, p->d_active,
+                           sweeps > 0 ? p->d_rhs2 : nullptr, p->d_ynorm2, p->opt.refine_tol, p->d_sspe,
+                           p->d_total, p->d_nbad));
+      break;
+    case 6:
+      HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      break;
+  }
+  return PCV_OK;
+}
+
+// Capture phases [ph0, ph1) on a private stream (so that the caller's stream
+// may be the null stream) and instantiate them as one graph.
+pcv_status capture_phases(pcv_problem* p, int ph0, int ph1, bool mixed, int sweeps, hipGraphExec_t* out) {
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  pcv_status s = PCV_OK;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) s = fail(PCV_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  if (e == hipSuccess) {
+    for (int ph = ph0; ph < ph1 && s == PCV_OK; ++ph) s = enqueue_phase(p, cs, ph, mixed, sweeps);
+    e = hipStreamEndCapture(cs, &g);
+    if (s == PCV_OK && e != hipSuccess) s = fail(PCV_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  if (s == PCV_OK) {
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      *out = nullptr;
+      s = fail(PCV_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  return s;
+}
+
+// Enqueue one theta-evaluation on the problem's stream: eagerly, as one
+// graph, or (when profiling with graphs) as one graph per phase with the
+// phase events recorded between them.
+pcv_status enqueue_eval(pcv_problem* p, bool mixed, int sweeps) {
+  hipStream_t st = p->stream;
+  const bool ev = p->events;
+  if (!p->opt.graph) {
+    for (int ph = 0; ph < N_PHASES; ++ph) {
+      pcv_status s = enqueue_phase(p, st, ph, mixed, sweeps);
+      if (s != PCV_OK) return s;
+      if (ev && ph < 6) HIPCHK(hipEventRecord(p->ev[ph], st));
+    }
+    return PCV_OK;
+  }
+  if (!ev) {
+    if (!p->graph_exec[0]) {
+      pcv_status s = capture_phases(p, 0, N_PHASES, mixed, sweeps, &p->graph_exec[0]);
+      if (s != PCV_OK) return s;
+    }
+    HIPCHK(hipGraphLaunch(p->graph_exec[0], st));
+    return PCV_OK;
+  }
+  for (int ph = 0; ph < N_PHASES; ++ph) {
+    if (!p->graph_exec[1 + ph]) {
+      pcv_status s = capture_phases(p, ph, ph + 1, mixed, sweeps, &p->graph_exec[1 + ph]);
+      if (s != PCV_OK) return s;
+    }
+    HIPCHK(hipGraphLaunch(p->graph_exec[1 + ph], st));
+    if (ph < 6) HIPCHK(hipEventRecord(p->ev[ph], st));
+  }
+  return PCV_OK;
+}
+
+}  // namespace
+
 pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep) {
   const double t0 = now_s();
   HIPCHK(hipSetDevice(p->device));
   const bool mixed = p->opt.prec == PCV_PREC_MIXED;
   pcv_status s = ensure_L(p, !mixed);
   if (s != PCV_OK) return s;
-  s = set_theta(p, th);
-  if (s != PCV_OK) return s;
-  Launch Lc{p->stream, p->d_desc, p->d_theta};
-  const bool ev = p->events;
-  if (ev) HIPCHK(hipEventRecord(p->ev[0], p->stream));
-  if (mixed)
-    HIPCHK(launch_potrf_f32(Lc, p->d_order_eval, p->n_active, p->d_px32, p->d_py32, p->d_L32, p->d_Inv,
-                            p->d_logdet, p->d_status));
-  else
-    HIPCHK(launch_potrf_f64(Lc, p->d_order_eval, p->n_active, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
-                            p->d_logdet, p->d_status));
-  if (ev) HIPCHK(hipEventRecord(p->ev[1], p->stream));
-  if (mixed) {
-    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_yT, nullptr, p->d_z,
-                               nullptr));
-    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z, p->d_alpha,
-                               nullptr));
-  } else {
-    HIPCHK(launch_trsv_fwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_yT, nullptr, p->d_z,
-                               nullptr));
-    HIPCHK(launch_trsv_bwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
-                               nullptr));
-  }
-  if (ev) HIPCHK(hipEventRecord(p->ev[2], p->stream));
+  set_theta_host(p, th);
   const int sweeps = mixed ? p->opt.max_refine : 0;
-  for (int it = 0; it < sweeps; ++it) {
-    HIPCHK(launch_residual(Lc, p->d_tile_items, (int)p->tile_items.size(), p->d_row_items,
-                           (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT, p->d_alpha, p->d_rrow,
-                           p->d_pcol, p->d_r));
-    HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, nullptr, p->d_r, p->d_z,
-                               p->d_rhs2));
-    HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z, p->d_x,
-                               p->d_alpha));
-  }
-  if (ev) HIPCHK(hipEventRecord(p->ev[3], p->stream));
-  HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx, p->d_vy,
-                            p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
-  if (ev) HIPCHK(hipEventRecord(p->ev[4], p->stream));
-  HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active,
-                       sweeps > 0 ? p->d_rhs2 : nullptr, p->d_ynorm2, p->opt.refine_tol, p->d_sspe,
-                       p->d_total, p->d_nbad));
-  if (ev) HIPCHK(hipEventRecord(p->ev[5], p->stream));
-  HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+  s = enqueue_eval(p, mixed, sweeps);
+  if (s != PCV_OK) return s;
   HIPCHK(hipStreamSynchronize(p->stream));
+  Launch Lc{p->stream, p->d_desc, p->d_theta};
 
   int32_t n_fallback = 0;
   const bool force_fb = mixed && (p->opt.debug_flags & 1) && p->n_active > 0;
@@ -490,9 +578,8 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     n_fallback = (int32_t)bad.size();
     s = ensure_L(p, true);
     if (s != PCV_OK) return s;
-    int32_t* d_bad = nullptr;
-    HIPCHK(hipMalloc((void**)&d_bad, sizeof(int32_t) * bad.size()));
-    HIPCHK(hipMemcpy(d_bad, bad.data(), sizeof(int32_t) * bad.size(), hipMemcpyHostToDevice));
+    int32_t* d_bad = p->d_bad;
+    HIPCHK(hipMemcpyAsync(d_bad, bad.data(), sizeof(int32_t) * bad.size(), hipMemcpyHostToDevice, p->stream));
     s = factor_solve64(p, p->d_theta, d_bad, (int)bad.size(), p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
                        p->d_logdet, p->d_status);
     if (s == PCV_OK) {
@@ -504,7 +591,6 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
       HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));
     }
-    (void)hipFree(d_bad);
     if (s != PCV_OK) return s;
     if (*p->h_nbad > 0) {
       HIPCHK(hipMemcpy(status.data(), p->d_status, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost));
@@ -538,7 +624,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     if (rep->per_subset_iters)
       for (int32_t i = 0; i < p->S; ++i) rep->per_subset_iters[i] = p->active[i] ? sweeps : 0;
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
-    if (ev) {
+    if (p->events) {
       float ms;
       HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
       rep->ms_factor = ms;

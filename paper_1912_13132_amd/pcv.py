@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("profile", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("debug_flags", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class EvalReport(ctypes.Structure):
@@ -147,7 +148,7 @@ class Problem:
 
     def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
                  prec="mixed", max_refine=1, refine_tol=1e-4, stream=None, mem_cap=0,
-                 profile=False, debug_flags=0):
+                 profile=False, debug_flags=0, graph=True):
         L = lib()
         self._locs = _as(locs, np.float64).reshape(-1, 2)
         self._y = _as(y, np.float64)
@@ -166,6 +167,7 @@ class Problem:
         opt.mem_cap_bytes = int(mem_cap)
         opt.profile = 1 if profile else 0
         opt.debug_flags = int(debug_flags)
+        opt.graph = 1 if graph else 0
         self.prec = prec
         h = ctypes.c_void_p()
         _check(L.pcv_problem_create(

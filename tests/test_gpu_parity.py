@@ -199,6 +199,35 @@ def test_refinement_convergence_test_falls_back(w_plain):
     assert 0.0 < rep["max_rel_residual"] <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_replays_match_eager(w_batched_small, prec):
+    """The captured evaluation, replayed for several theta with eager
+    evaluations and host synchronisations in between, gives every replay
+    bit for bit the eager result (loss, per-subset SSPE and log det)."""
+    g = W.theta_grid(w_batched_small.theta_true, 3)
+    ths = [pcv.theta(*t) for t in g] + [pcv.theta(*g[0])]
+    say(f"[case] graph replays prec={prec}")
+    with pcv.Problem.from_workload(w_batched_small, prec=prec, graph=True, profile=True) as Pg, \
+            pcv.Problem.from_workload(w_batched_small, prec=prec, graph=False) as Pe:
+        for th in ths:
+            a, ra = Pg.eval(th, report=True)
+            b, rb = Pe.eval(th, report=True)
+            assert a == b
+            np.testing.assert_array_equal(ra["per_subset_sspe"], rb["per_subset_sspe"])
+            np.testing.assert_array_equal(ra["per_subset_logdet"], rb["per_subset_logdet"])
+            assert ra["ms_factor"] > 0.0
+
+
+def test_graph_with_fallback_matches_fp64(w_plain):
+    th = pcv.theta(0.1, 0.05)
+    say("[case] graph + forced fallback")
+    with pcv.Problem.from_workload(w_plain, prec="mixed", debug_flags=1, graph=True) as P:
+        a = [P.eval(th) for _ in range(3)]
+    with pcv.Problem.from_workload(w_plain, prec="fp64", graph=False) as P:
+        ref = P.eval(th)
+    assert a == [ref] * 3
+
+
 def test_repeatable_bitwise(w_batched_small):
     """Two evaluations of the same theta are bitwise equal (fixed-order sums)."""
     th = pcv.theta(0.05, 0.1)
