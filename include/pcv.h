@@ -102,13 +102,22 @@ typedef struct {
   int32_t n_fallback_fp64;   /* mixed: subsets re-run in FP64                       */
   int32_t max_refine_iters;  /* mixed: largest number of sweeps any subset used     */
   int32_t pad0;
-  double max_rel_residual;   /* mixed: max_i ||r_i|| / ||y_i|| after refinement     */
+  double max_rel_residual;   /* mixed: max_i ||r_i|| / ||y_i|| of the residual the
+                                last refinement sweep corrected                     */
   double seconds;            /* wall time of the call                               */
   /* phase times in ms (HIP events on the evaluation stream), when profiling */
   double ms_factor, ms_solve, ms_refine, ms_predict, ms_reduce;
   double* per_subset_sspe;   /* optional out [S]: z_i (0 for skipped subsets)       */
   double* per_subset_logdet; /* optional out [S]: log det(Sigma_i + lambda I)       */
   int32_t* per_subset_iters; /* optional out [S]: refinement sweeps used            */
+  /* Composite likelihood over the evaluated subsets (Sec. 2.1, eq. (2) applied
+   * to each subset's training data, tau = lambda sigma^2):
+   *   -2 l_i = n_i log(2 pi) + n_i log sigma^2 + log det(Sigma_i + lambda I)
+   *            + y_i^T (Sigma_i + lambda I)^{-1} y_i / sigma^2.
+   * In mixed precision the log det comes from the FP32 factor (relative
+   * error ~1e-6 of |log det|); the quadratic term uses the refined alpha. */
+  double neg2loglik;              /* sum of -2 l_i                                  */
+  double* per_subset_neg2loglik;  /* optional out [S] (0 for skipped subsets)       */
 } pcv_eval_report;
 
 typedef struct pcv_problem pcv_problem;
@@ -154,9 +163,23 @@ pcv_status pcv_eval(pcv_problem* p, const pcv_theta* theta, double* loss,
 pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas,
                           double* losses);
 
+/* Local losses over a set of theta values (Sec. 4.4: local RMSPE and the
+ * best local zeta of each subset, the basis of non-stationary fits).
+ * losses[k] as pcv_eval for thetas[k]; per_subset_sspe (may be NULL) receives
+ * z_i(theta_k) at [k * S + i]; best (may be NULL) receives, per subset, the k
+ * with the smallest z_i (lowest k on ties; -1 for subsets without
+ * validation points). */
+pcv_status pcv_eval_grid(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,
+                         double* per_subset_sspe, int32_t* best);
+
 /* Factor every subset at theta in FP64 and keep L_i and
  * alpha_i = (Sigma_i + lambda I)^{-1} y_i resident for pcv_predict. */
 pcv_status pcv_factor(pcv_problem* p, const pcv_theta* theta);
+
+/* As pcv_factor, but subset i at its own thetas[i] (host array [S]): local
+ * zeta, so that pcv_predict gives the non-stationary predictions the paper
+ * suggests in Sec. 5 (each query uses its owning subset's parameters). */
+pcv_status pcv_factor_local(pcv_problem* p, const pcv_theta* thetas);
 
 /* Kriging at q query locations (host float64 [q][2]) from the factors of
  * the last pcv_factor: each query is routed to its core (half-open

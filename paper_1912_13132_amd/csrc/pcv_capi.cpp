@@ -171,12 +171,59 @@ pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thet
   return PCV_OK;
 }
 
+pcv_status pcv_eval_grid(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,
+                         double* per_subset_sspe, int32_t* best) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (n_theta < 0 || (n_theta > 0 && (!thetas || !losses))) return fail(PCV_ERR_INVALID, "bad grid arguments");
+  for (int32_t k = 0; k < n_theta; ++k) {
+    pcv_status s = check_theta(&thetas[k]);
+    if (s != PCV_OK) return fail(s, "theta[" + std::to_string(k) + "]: " + pcv::g_err);
+  }
+  const int32_t S = p->S;
+  std::vector<double> own;
+  double* z = per_subset_sspe;
+  if (!z && best) {
+    own.resize((size_t)n_theta * S);
+    z = own.data();
+  }
+  for (int32_t k = 0; k < n_theta; ++k) {
+    pcv_eval_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    rep.per_subset_sspe = z ? z + (size_t)k * S : nullptr;
+    pcv_status s = pcv::eval_impl(p, thetas[k], &losses[k], z ? &rep : nullptr);
+    if (s != PCV_OK) return s;
+  }
+  if (best)
+    for (int32_t i = 0; i < S; ++i) {
+      int32_t b = -1;
+      if (p->active[i] && n_theta > 0) {
+        b = 0;
+        for (int32_t k = 1; k < n_theta; ++k)
+          if (z[(size_t)k * S + i] < z[(size_t)b * S + i]) b = k;
+      }
+      best[i] = b;
+    }
+  return PCV_OK;
+}
+
 pcv_status pcv_factor(pcv_problem* p, const pcv_theta* theta) {
   pcv::g_err.clear();
   if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
   pcv_status s = check_theta(theta);
   if (s != PCV_OK) return s;
-  return pcv::factor_impl(p, *theta);
+  return pcv::factor_impl(p, theta, false);
+}
+
+pcv_status pcv_factor_local(pcv_problem* p, const pcv_theta* thetas) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (!thetas) return fail(PCV_ERR_INVALID, "thetas is NULL");
+  for (int32_t i = 0; i < p->S; ++i) {
+    pcv_status s = check_theta(thetas + i);
+    if (s != PCV_OK) return fail(s, "thetas[" + std::to_string(i) + "]: " + pcv::g_err);
+  }
+  return pcv::factor_impl(p, thetas, true);
 }
 
 pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,

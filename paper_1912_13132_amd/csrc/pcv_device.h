@@ -25,7 +25,8 @@ struct SubsetDesc {
   int64_t offL;    // packed tile-row lower factor                 [packed_size(npad)]
   int64_t offInv;  // inverse diagonal blocks, FP64                [npad * TB]
   int64_t offPC;   // residual column partials, FP64               [TB * nb (nb - 1) / 2]
-  int32_t n, m, npad, id;
+  int32_t n, m, npad;
+  int32_t th;      // theta slot: kernels read theta[th]
 };
 
 // The evaluated parameters, read by every kernel from device memory so that
@@ -113,6 +114,9 @@ hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* t
                         const double* L64, const double* Inv, const double* alpha, const double* qx,
                         const double* qy, const int32_t* qorig, const int32_t* qflag,
                         double* Wscratch, double* mean, double* var);
+// quad[order[k]] = y_T^T alpha of subset order[k], k < n_items.
+hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n_items,
+                       const double* yT, const double* alpha, double* quad);
 // Per-subset SSPE and the global loss (fixed-order compensated sums), count
 // of subsets with nonzero status.  With rhs2 non-null, an active subset with
 // rhs2[i] > tol^2 * ynorm2[i] gets status PCV_STATUS_STAGNATED first.

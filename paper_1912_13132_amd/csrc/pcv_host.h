@@ -58,7 +58,7 @@ struct pcv_problem {
   double *d_vx = nullptr, *d_vy = nullptr, *d_yV = nullptr;
   double *d_z = nullptr, *d_x = nullptr, *d_alpha = nullptr, *d_r = nullptr, *d_rhs2 = nullptr;
   double *d_yhat = nullptr, *d_err = nullptr;
-  double *d_logdet = nullptr, *d_sspe = nullptr;
+  double *d_logdet = nullptr, *d_sspe = nullptr, *d_quad = nullptr;
   int32_t* d_status = nullptr;
   int32_t* d_bad = nullptr;         // subsets re-run in FP64
   // captured theta-evaluation: [0] whole, [1 + k] phase k (when profiling)
@@ -77,7 +77,9 @@ struct pcv_problem {
   double* d_zf = nullptr;
   double* d_logdetf = nullptr;
   int32_t* d_statusf = nullptr;
-  pcv::ThetaDev* d_theta_fact = nullptr;
+  pcv::ThetaDev* d_theta_fact = nullptr;      // [S]: slot 0, or slot i per subset
+  pcv::SubsetDesc* d_desc_local = nullptr;    // descriptors with th = i
+  const pcv::SubsetDesc* d_desc_fact = nullptr;  // descriptors the factors were made with
 
   // pinned host mirrors
   pcv::ThetaDev* h_theta = nullptr;
@@ -101,7 +103,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
                          const int32_t* val_idx, const double* core_rect);
 void problem_free(pcv_problem* p);
 pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep);
-pcv_status factor_impl(pcv_problem* p, const pcv_theta& th);
+pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
                         int32_t obs_noise, int32_t* owner);
 pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,

@@ -289,8 +289,8 @@ __global__ __launch_bounds__(256, 2) void k_residual_tiles(const SubsetDesc* __r
   const int I = it.y, n = D.n;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int ri = l >> 3, cj = l & 7;
-  const int cov = theta->cov;
-  const double ir = theta->inv_range;
+  const int cov = theta[D.th].cov;
+  const double ir = theta[D.th].inv_range;
   const double* __restrict__ X = tx + D.offT;
   const double* __restrict__ Y = ty + D.offT;
   const double* __restrict__ a = alphabuf + D.offP;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(64) void k_residual_reduce(const SubsetDesc* __rest
   if (row < n) {
     double s = rrow[D.offP + row];
     for (int I = J + 1; I < nb; ++I) s += pcol[D.offPC + ((int64_t)I * (I - 1) / 2 + J) * 64 + threadIdx.x];
-    r = yT[D.offT + row] - theta->lambda * alphabuf[D.offP + row] - s;
+    r = yT[D.offT + row] - theta[D.th].lambda * alphabuf[D.offP + row] - s;
   }
   rbuf[D.offP + row] = r;
 }
@@ -409,8 +409,8 @@ __global__ __launch_bounds__(256) void k_predict_val(const SubsetDesc* __restric
   const int n = D.n, m = D.m;
   const int tid = threadIdx.x, q = tid >> 6, l = tid & 63;
   const int v = it.y * 64 + l;
-  const int cov = theta->cov;
-  const double ir = theta->inv_range;
+  const int cov = theta[D.th].cov;
+  const double ir = theta[D.th].inv_range;
   const double* __restrict__ X = tx + D.offT;
   const double* __restrict__ Y = ty + D.offT;
   const double* __restrict__ a = alphabuf + D.offP;
@@ -498,6 +498,30 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
   }
 }
 
+// ---------------------------------------------------------------------------
+// Quadratic term of the subset likelihood (eq. (2)): y_T^T alpha with
+// alpha = M^{-1} y_T, one workgroup per subset, fixed-order sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_quad(const SubsetDesc* __restrict__ desc,
+                                              const int32_t* __restrict__ order,
+                                              const double* __restrict__ yT,
+                                              const double* __restrict__ alphabuf,
+                                              double* __restrict__ quad) {
+  __shared__ double red[256];
+  const int sidx = order[blockIdx.x];
+  const SubsetDesc D = desc[sidx];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int r = tid; r < D.n; r += 256) s = fma(yT[D.offT + r], alphabuf[D.offP + r], s);
+  red[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) quad[sidx] = red[0];
+}
+
 // ------------------------------------------------------------- launchers --
 template <typename T>
 static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items, int max_npad, const T* Lbuf,
@@ -561,6 +585,13 @@ hipError_t launch_predict_val(const Launch& Lc, const int2* items, int n_items, 
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_predict_val, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, items, Lc.theta,
                      tx, ty, vx, vy, yV, alpha, yhat, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n_items,
+                       const double* yT, const double* alpha, double* quad) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quad, dim3(n_items), dim3(256), 0, s, desc, order, yT, alpha, quad);
   return hipGetLastError();
 }
 

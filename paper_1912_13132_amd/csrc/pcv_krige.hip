@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_krige(const SubsetDesc* __restrict__ de
   const SubsetDesc D = desc[it.sidx];
   const int n = D.n, nb = D.npad / TB;
   const int tid = threadIdx.x, g = tid >> 6, l = tid & 63;
-  const int cov = theta->cov;
-  const double ir = theta->inv_range;
+  const int cov = theta[D.th].cov;
+  const double ir = theta[D.th].inv_range;
   const double* __restrict__ X = tx + D.offT;
   const double* __restrict__ Y = ty + D.offT;
   const double* __restrict__ a = alphabuf + D.offP;
@@ -164,9 +164,9 @@ __global__ __launch_bounds__(256) void k_krige(const SubsetDesc* __restrict__ de
       const int32_t o = qorig[it.q0 + q];
       mean[o] = m;
       if (f & KRIGE_VAR) {
-        const double s2 = theta->sigma2;
+        const double s2 = theta[D.th].sigma2;
         double v = s2 * (1.0 - s2w);
-        if (f & KRIGE_OBS_NOISE) v += s2 * theta->lambda;
+        if (f & KRIGE_OBS_NOISE) v += s2 * theta[D.th].lambda;
         var[o] = v;
       }
     }

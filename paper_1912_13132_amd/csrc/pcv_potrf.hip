@@ -315,9 +315,9 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
   double* __restrict__ Inv = Invbuf + D.offInv;
   const T* __restrict__ X = cx + D.offP;  // padded coordinates (npad entries)
   const T* __restrict__ Y = cy + D.offP;
-  const int cov = theta->cov;
-  const T ir = (T)theta->inv_range;
-  const double lam64 = theta->lambda;
+  const int cov = theta[D.th].cov;
+  const T ir = (T)theta[D.th].inv_range;
+  const double lam64 = theta[D.th].lambda;
 
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int lr = l & 15, g = l >> 4;

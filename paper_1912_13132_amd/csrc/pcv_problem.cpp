@@ -251,7 +251,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     d.n = (int32_t)(tptr[i + 1] - tptr[i]);
     d.m = (int32_t)(vptr[i + 1] - vptr[i]);
     d.npad = (d.n + TB - 1) / TB * TB;
-    d.id = i;
+    d.th = 0;
     d.offT = offT;
     d.offV = offV;
     d.offP = offP;
@@ -373,6 +373,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(dalloc(p, &p->d_err, (size_t)p->nnzV));
   TRY(dalloc(p, &p->d_logdet, (size_t)S));
   TRY(dalloc(p, &p->d_sspe, (size_t)S));
+  TRY(dalloc(p, &p->d_quad, (size_t)S));
   TRY(dalloc(p, &p->d_status, (size_t)S));
   TRY(dalloc(p, &p->d_bad, (size_t)S));
   TRY(dalloc(p, &p->d_theta, 1));
@@ -412,10 +413,10 @@ namespace {
 
 // Factor + solve alpha = M^{-1} y_T in FP64 for the subsets in `d_order`
 // (device list of `count` subset ids) into the given buffers.
-pcv_status factor_solve64(pcv_problem* p, const ThetaDev* d_theta, const int32_t* d_order, int count,
-                          double* Lb, double* Invb, double* zb, double* alphab, double* logdetb,
-                          int32_t* statusb) {
-  Launch Lc{p->stream, p->d_desc, d_theta};
+pcv_status factor_solve64(pcv_problem* p, const SubsetDesc* d_desc, const ThetaDev* d_theta,
+                          const int32_t* d_order, int count, double* Lb, double* Invb, double* zb,
+                          double* alphab, double* logdetb, int32_t* statusb) {
+  Launch Lc{p->stream, d_desc, d_theta};
   HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_px64, p->d_py64, Lb, Invb, logdetb, statusb));
   HIPCHK(launch_trsv_fwd_f64(Lc, d_order, count, p->max_npad, Lb, Invb, p->d_yT, nullptr, zb, nullptr));
   HIPCHK(launch_trsv_bwd_f64(Lc, d_order, count, p->max_npad, Lb, Invb, zb, alphab, nullptr));
@@ -474,6 +475,7 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
     case 4:
       HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
                                 p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
+      HIPCHK(launch_quad(st, p->d_desc, p->d_order_eval, p->n_active, p->d_yT, p->d_alpha, p->d_quad));
       break;
     case 5:
       HIPCHK(launch_reduce(st, p->d_desc, p->S, p->d_err, p->d_status, p->d_active,
@@ -580,11 +582,12 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     if (s != PCV_OK) return s;
     int32_t* d_bad = p->d_bad;
     HIPCHK(hipMemcpyAsync(d_bad, bad.data(), sizeof(int32_t) * bad.size(), hipMemcpyHostToDevice, p->stream));
-    s = factor_solve64(p, p->d_theta, d_bad, (int)bad.size(), p->d_L64, p->d_Inv, p->d_z, p->d_alpha,
-                       p->d_logdet, p->d_status);
+    s = factor_solve64(p, p->d_desc, p->d_theta, d_bad, (int)bad.size(), p->d_L64, p->d_Inv, p->d_z,
+                       p->d_alpha, p->d_logdet, p->d_status);
     if (s == PCV_OK) {
       HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
                                 p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
+      HIPCHK(launch_quad(p->stream, p->d_desc, p->d_order_eval, p->n_active, p->d_yT, p->d_alpha, p->d_quad));
       HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, nullptr,
                            nullptr, 0.0, p->d_sspe, p->d_total, p->d_nbad));
       HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
@@ -623,6 +626,26 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     }
     if (rep->per_subset_iters)
       for (int32_t i = 0; i < p->S; ++i) rep->per_subset_iters[i] = p->active[i] ? sweeps : 0;
+    {
+      // composite likelihood, summed in subset order with compensation
+      std::vector<double> ld(p->S), qd(p->S);
+      HIPCHK(hipMemcpy(ld.data(), p->d_logdet, sizeof(double) * p->S, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(qd.data(), p->d_quad, sizeof(double) * p->S, hipMemcpyDeviceToHost));
+      const double l2pi = std::log(2.0 * M_PI), ls2 = std::log(th.sigma2);
+      double sum = 0.0, comp = 0.0;
+      for (int32_t i = 0; i < p->S; ++i) {
+        double v = 0.0;
+        if (p->active[i]) {
+          const double n = (double)p->desc[i].n;
+          v = n * l2pi + n * ls2 + ld[i] + qd[i] / th.sigma2;
+          const double t = sum + v;
+          comp += std::fabs(sum) >= std::fabs(v) ? (sum - t) + v : (v - t) + sum;
+          sum = t;
+        }
+        if (rep->per_subset_neg2loglik) rep->per_subset_neg2loglik[i] = v;
+      }
+      rep->neg2loglik = sum + comp;
+    }
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
     if (p->events) {
       float ms;
@@ -642,7 +665,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   return PCV_OK;
 }
 
-pcv_status factor_impl(pcv_problem* p, const pcv_theta& th) {
+pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local) {
   HIPCHK(hipSetDevice(p->device));
   p->factored = false;
   pcv_status s = PCV_OK;
@@ -653,26 +676,36 @@ pcv_status factor_impl(pcv_problem* p, const pcv_theta& th) {
     if ((s = dalloc(p, &p->d_zf, (size_t)p->nP)) != PCV_OK) return s;
     if ((s = dalloc(p, &p->d_logdetf, (size_t)p->S)) != PCV_OK) return s;
     if ((s = dalloc(p, &p->d_statusf, (size_t)p->S)) != PCV_OK) return s;
-    if ((s = dalloc(p, &p->d_theta_fact, 1)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_theta_fact, (size_t)p->S)) != PCV_OK) return s;
   }
-  ThetaDev h;
-  h.cov = th.cov;
-  h.pad = 0;
-  h.range = th.range;
-  h.inv_range = 1.0 / th.range;
-  h.lambda = th.lambda;
-  h.sigma2 = th.sigma2;
-  HIPCHK(hipMemcpyAsync(p->d_theta_fact, &h, sizeof(ThetaDev), hipMemcpyHostToDevice, p->stream));
+  // one theta for every subset (slot 0), or subset i's own theta in slot i
+  if (local && !p->d_desc_local) {
+    std::vector<SubsetDesc> dl = p->desc;
+    for (int32_t i = 0; i < p->S; ++i) dl[i].th = i;
+    if ((s = upload(p, &p->d_desc_local, dl)) != PCV_OK) return s;
+  }
+  const int nth = local ? p->S : 1;
+  std::vector<ThetaDev> h(nth);
+  for (int k = 0; k < nth; ++k) {
+    h[k].cov = th[k].cov;
+    h[k].pad = 0;
+    h[k].range = th[k].range;
+    h[k].inv_range = 1.0 / th[k].range;
+    h[k].lambda = th[k].lambda;
+    h[k].sigma2 = th[k].sigma2;
+  }
+  HIPCHK(hipMemcpyAsync(p->d_theta_fact, h.data(), sizeof(ThetaDev) * nth, hipMemcpyHostToDevice, p->stream));
+  p->d_desc_fact = local ? p->d_desc_local : p->d_desc;
   const int count = (int)p->order_all.size();
-  s = factor_solve64(p, p->d_theta_fact, p->d_order_all, count, p->d_Lf, p->d_Invf, p->d_zf, p->d_alpha_fact,
-                     p->d_logdetf, p->d_statusf);
+  s = factor_solve64(p, p->d_desc_fact, p->d_theta_fact, p->d_order_all, count, p->d_Lf, p->d_Invf, p->d_zf,
+                     p->d_alpha_fact, p->d_logdetf, p->d_statusf);
   if (s != PCV_OK) return s;
   std::vector<int32_t> status(p->S);
   HIPCHK(hipMemcpyAsync(status.data(), p->d_statusf, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   for (int32_t i : p->order_all)
     if (status[i]) return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(i) + " is not positive definite in FP64");
-  p->fact_theta = th;
+  p->fact_theta = th[0];
   p->factored = true;
   return PCV_OK;
 }
@@ -710,7 +743,7 @@ pcv_status predict_impl(pcv_problem* p, int64_t q, const double* ql, double* mea
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_items, P.items.data(), sizeof(KrigeItem) * ni, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess)
-    e = launch_krige(p->stream, p->d_desc, p->d_theta_fact, d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
+    e = launch_krige(p->stream, p->d_desc_fact, p->d_theta_fact, d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
                      p->d_Invf, p->d_alpha_fact, d_qx, d_qy, d_qorig, d_qflag, d_W, d_mean, d_var);
   if (e == hipSuccess) e = hipMemcpyAsync(mean, d_mean, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess && var) e = hipMemcpyAsync(var, d_var, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);

@@ -231,7 +231,7 @@ void batcher(pcv_server* s) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(KrigeItem) * ni, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-      e = launch_krige(st, p->d_desc, p->d_theta_fact, sl.d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
+      e = launch_krige(st, p->d_desc_fact, p->d_theta_fact, sl.d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
                        p->d_Invf, p->d_alpha_fact, sl.d_qx, sl.d_qy, sl.d_qorig, sl.d_qflag, sl.d_W,
                        sl.d_mean, sl.d_var);
     if (e == hipSuccess) e = hipMemcpyAsync(sl.h_mean, sl.d_mean, 8 * nq, hipMemcpyDeviceToHost, st);

@@ -56,7 +56,8 @@ class EvalReport(ctypes.Structure):
                 ("ms_refine", ctypes.c_double), ("ms_predict", ctypes.c_double),
                 ("ms_reduce", ctypes.c_double),
                 ("per_subset_sspe", _c_double_p), ("per_subset_logdet", _c_double_p),
-                ("per_subset_iters", _c_int32_p)]
+                ("per_subset_iters", _c_int32_p), ("neg2loglik", ctypes.c_double),
+                ("per_subset_neg2loglik", _c_double_p)]
 
 
 class ServerReport(ctypes.Structure):
@@ -91,6 +92,9 @@ def lib():
     L.pcv_eval.argtypes = [P, ctypes.POINTER(Theta), _c_double_p, ctypes.POINTER(EvalReport)]
     L.pcv_eval_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p]
     L.pcv_factor.argtypes = [P, ctypes.POINTER(Theta)]
+    L.pcv_factor_local.argtypes = [P, ctypes.POINTER(Theta)]
+    L.pcv_eval_grid.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p, _c_double_p,
+                                _c_int32_p]
     L.pcv_predict.argtypes = [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
                               ctypes.c_int32, _c_int32_p]
     L.pcv_problem_destroy.argtypes = [P]
@@ -109,7 +113,8 @@ def lib():
     L.pcv_last_error.argtypes = []
     L.pcv_last_error.restype = ctypes.c_char_p
     for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
-              "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create",
+              "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create", "pcv_factor_local",
+              "pcv_eval_grid",
               "pcv_server_submit_predict", "pcv_server_submit_eval", "pcv_server_wait",
               "pcv_server_stats", "pcv_server_report_get", "pcv_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
@@ -204,10 +209,13 @@ class Problem:
         rep.per_subset_sspe = _ptr(z, ctypes.c_double)
         rep.per_subset_logdet = _ptr(ld, ctypes.c_double)
         rep.per_subset_iters = _ptr(it, ctypes.c_int32)
+        nll = np.zeros(self.S)
+        rep.per_subset_neg2loglik = _ptr(nll, ctypes.c_double)
         _check(L.pcv_eval(self._handle(), ctypes.byref(th), ctypes.byref(loss), ctypes.byref(rep)))
         d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
              if not k.startswith("per_subset") and k != "pad0"}
-        d.update(per_subset_sspe=z, per_subset_logdet=ld, per_subset_iters=it)
+        d.update(per_subset_sspe=z, per_subset_logdet=ld, per_subset_iters=it,
+                 per_subset_neg2loglik=nll)
         return loss.value, d
 
     def eval_batch(self, thetas):
@@ -217,8 +225,27 @@ class Problem:
         _check(L.pcv_eval_batch(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double)))
         return out
 
+    def eval_grid(self, thetas):
+        """Losses, per-subset losses [K][S] and the best local theta index of
+        each subset (-1 where nothing is evaluated)."""
+        K = len(thetas)
+        arr = (Theta * K)(*thetas)
+        losses = np.zeros(K)
+        z = np.zeros((K, self.S))
+        best = np.zeros(self.S, dtype=np.int32)
+        _check(lib().pcv_eval_grid(self._handle(), K, arr, _ptr(losses, ctypes.c_double),
+                                   _ptr(z, ctypes.c_double), _ptr(best, ctypes.c_int32)))
+        return losses, z, best
+
     def factor(self, th):
         _check(lib().pcv_factor(self._handle(), ctypes.byref(th)))
+
+    def factor_local(self, thetas):
+        """Factor subset i at thetas[i] (len(thetas) == S)."""
+        if len(thetas) != self.S:
+            raise PcvError(1, f"need {self.S} theta values, got {len(thetas)}")
+        arr = (Theta * self.S)(*thetas)
+        _check(lib().pcv_factor_local(self._handle(), arr))
 
     def predict(self, q, want_var=True, obs_noise=False):
         q = _as(q, np.float64).reshape(-1, 2)

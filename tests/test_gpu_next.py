@@ -1,0 +1,98 @@
+"""GPU checks of the per-subset likelihood, the local-theta grid evaluation
+and the local-theta factorisation against the FP64 oracle.
+
+Tolerances: FP64 path 1e-10 relative on -2 log-likelihood per subset.  In
+mixed precision the log det comes from the FP32 factor: its relative error
+is bounded by ~n * 2^-24 per pivot in the worst case; the test allows 1e-5
+of |-2 l_i| and reports the largest difference seen.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_13132_amd import pcv
+from paper_1912_13132_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def w_small():
+    return W.scaled("batched", 0.05)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_composite_likelihood_per_subset(w_small, prec, tol):
+    pt = w_small.part
+    th = pcv.theta(0.05, 0.1, sigma2=0.7)
+    say(f"[case] likelihood prec={prec}")
+    with pcv.Problem.from_workload(w_small, prec=prec) as P:
+        _, rep = P.eval(th, report=True)
+    got = rep["per_subset_neg2loglik"]
+    ref = np.zeros(pt.n_subsets)
+    for i in range(pt.n_subsets):
+        if pt.val_ptr[i + 1] == pt.val_ptr[i]:
+            continue
+        T = pt.train_idx[pt.train_ptr[i]:pt.train_ptr[i + 1]]
+        ref[i] = oracle.neg2_loglik_subset(w_small.locs[T], w_small.y[T], 0, 0.05, 0.1, 0.7)
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    say(f"   max rel diff {rel.max():.2e}")
+    assert rel.max() <= tol
+    assert abs(rep["neg2loglik"] - ref.sum()) <= tol * np.abs(ref).sum()
+
+
+def test_local_best_theta_over_a_grid(w_small):
+    pt = w_small.part
+    g = W.theta_grid(w_small.theta_true, 3)
+    ths = [pcv.theta(*t) for t in g]
+    say("[case] local best theta over a 3x3 grid")
+    with pcv.Problem.from_workload(w_small, prec="mixed") as P:
+        losses, z, best = P.eval_grid(ths)
+    zr = np.array([oracle.cv_loss(w_small.locs, w_small.y, pt.train_ptr, pt.train_idx, pt.val_ptr,
+                                  pt.val_idx, 0, r_, l_)["per_subset_sspe"] for r_, l_ in g])
+    np.testing.assert_allclose(z, zr, rtol=1e-5, atol=1e-12)
+    act = np.diff(pt.val_ptr) > 0
+    assert np.all(best[~act] == -1)
+    for i in np.nonzero(act)[0]:
+        order = np.argsort(zr[:, i], kind="stable")
+        k0, k1 = order[0], order[1]
+        # where the two best differ by more than the tolerance the argmin is unique
+        if zr[k1, i] - zr[k0, i] > 1e-5 * zr[k0, i]:
+            assert best[i] == k0
+        else:
+            assert best[i] in (k0, k1)
+    np.testing.assert_allclose(losses, zr.sum(axis=1), rtol=1e-6)
+
+
+def test_local_theta_factorisation_predicts_with_each_subsets_theta(w_small):
+    pt = w_small.part
+    S = pt.n_subsets
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 800]))
+    loc_th = [(0.05 * 2 ** r.uniform(-1, 1), 0.1 * 2 ** r.uniform(-1, 1)) for _ in range(S)]
+    ths = [pcv.theta(a, b, sigma2=1.2) for a, b in loc_th]
+    lo, hi = w_small.locs.min(0), w_small.locs.max(0)
+    q = r.uniform(lo, hi, (400, 2))
+    say("[case] local theta factorisation")
+    with pcv.Problem.from_workload(w_small, prec="mixed") as P:
+        P.factor_local(ths)
+        mean, var, owner = P.predict(q)
+        # the same theta everywhere gives exactly pcv_factor's predictions
+        P.factor_local([pcv.theta(0.05, 0.1, sigma2=1.2)] * S)
+        m1, v1, _ = P.predict(q)
+        P.factor(pcv.theta(0.05, 0.1, sigma2=1.2))
+        m2, v2, _ = P.predict(q)
+    np.testing.assert_array_equal(m1, m2)
+    np.testing.assert_array_equal(v1, v2)
+    for s in np.unique(owner):
+        sel = owner == s
+        T = pt.train_idx[pt.train_ptr[s]:pt.train_ptr[s + 1]]
+        mo, vo = oracle.predict(w_small.locs[T], w_small.y[T], q[sel], 0, loc_th[s][0], loc_th[s][1],
+                                sigma2=1.2)
+        np.testing.assert_allclose(mean[sel], mo, rtol=1e-9, atol=1e-10)
+        np.testing.assert_allclose(var[sel], vo, rtol=1e-9, atol=1e-10)
