@@ -191,6 +191,18 @@ pcv_status pcv_factor_local(pcv_problem* p, const pcv_theta* thetas);
 pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* mean,
                        double* var, int32_t obs_noise, int32_t* owner);
 
+/* Generalised least squares estimate of a linear mean in each subset (Sec. 5,
+ * eq. (8)): beta_i = (X_i^T M_i^{-1} X_i)^{-1} X_i^T M_i^{-1} y_i through the
+ * FP64 factors of the last pcv_factor / pcv_factor_local.
+ *   X       host float64 [n][n_cov], covariates of every location (row-major),
+ *           1 <= n_cov <= 8
+ *   beta    host float64 [S][n_cov] out; NaN for subsets without training
+ *           points or whose normal matrix is not positive definite
+ *   status  host int32 [S] out (may be NULL): 0 fine, j + 1 normal matrix not
+ *           positive definite at column j, -1 no training points
+ * Errors: PCV_ERR_INVALID, PCV_ERR_STATE (before pcv_factor). */
+pcv_status pcv_gls(pcv_problem* p, int32_t n_cov, const double* X, double* beta, int32_t* status);
+
 pcv_status pcv_problem_destroy(pcv_problem* p);
 
 /* Sizes of the problem: subsets, total training memberships, largest

@@ -215,6 +215,17 @@ pcv_status pcv_factor(pcv_problem* p, const pcv_theta* theta) {
   return pcv::factor_impl(p, theta, false);
 }
 
+pcv_status pcv_gls(pcv_problem* p, int32_t n_cov, const double* X, double* beta, int32_t* status) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (n_cov < 1 || n_cov > pcv::GLS_MAXP) return fail(PCV_ERR_INVALID, "n_cov must be in [1, 8]");
+  if (!X || !beta) return fail(PCV_ERR_INVALID, "X or beta is NULL");
+  for (int64_t j = 0; j < p->n * n_cov; ++j)
+    if (!is_finite(X[j])) return fail(PCV_ERR_INVALID, "non-finite covariate");
+  if (!p->factored) return fail(PCV_ERR_STATE, "pcv_gls called before pcv_factor");
+  return pcv::gls_impl(p, n_cov, X, beta, status);
+}
+
 pcv_status pcv_factor_local(pcv_problem* p, const pcv_theta* thetas) {
   pcv::g_err.clear();
   if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");

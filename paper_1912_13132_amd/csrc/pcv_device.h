@@ -114,6 +114,14 @@ hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* t
                         const double* L64, const double* Inv, const double* alpha, const double* qx,
                         const double* qy, const int32_t* qorig, const int32_t* qflag,
                         double* Wscratch, double* mean, double* var);
+// GLS coefficients (p <= GLS_MAXP covariates): X and W = M^{-1} X as p
+// padded vectors of nP entries each (column j at j * nP + offP); beta
+// [S][p]; status[i] = j + 1 when the normal matrix is not positive
+// definite at column j (beta then NaN).
+constexpr int GLS_MAXP = 8;
+hipError_t launch_gls(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n_items, int p,
+                      int64_t nP, const double* Xp, const double* Wp, const double* alpha, double* beta,
+                      int32_t* status);
 // quad[order[k]] = y_T^T alpha of subset order[k], k < n_items.
 hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n_items,
                        const double* yT, const double* alpha, double* quad);

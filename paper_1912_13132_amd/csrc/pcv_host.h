@@ -36,6 +36,8 @@ struct pcv_problem {
   pcv_router router;
   std::vector<double> centroid;     // S x 2
   std::vector<double> ynorm2;       // S: ||y_T||^2
+  std::vector<int64_t> train_ptr;   // S + 1 (training CSR, kept for covariates)
+  std::vector<int32_t> train_idx;
   int64_t nnzT = 0, nnzV = 0, nP = 0, nL = 0, nInv = 0, n_val_total = 0;
   int32_t max_train = 0;
   int32_t max_npad = 0;
@@ -104,6 +106,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
 void problem_free(pcv_problem* p);
 pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep);
 pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local);
+pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta, int32_t* status);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
                         int32_t obs_noise, int32_t* owner);
 pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,

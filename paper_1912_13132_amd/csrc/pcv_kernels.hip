@@ -522,6 +522,95 @@ __global__ __launch_bounds__(256) void k_quad(const SubsetDesc* __restrict__ des
   if (tid == 0) quad[sidx] = red[0];
 }
 
+// ---------------------------------------------------------------------------
+// GLS mean coefficients (Sec. 5, eq. (8)) of one subset from W = M^{-1} X
+// and alpha = M^{-1} y: beta solves (X^T W) beta = X^T alpha.  The p x p
+// system (p <= GLS_MAXP) is factored by one thread.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wsum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_gls(const SubsetDesc* __restrict__ desc,
+                                             const int32_t* __restrict__ order, int p, int64_t nP,
+                                             const double* __restrict__ Xp,
+                                             const double* __restrict__ Wp,
+                                             const double* __restrict__ alphabuf,
+                                             double* __restrict__ beta, int32_t* __restrict__ status) {
+  constexpr int NA = GLS_MAXP * (GLS_MAXP + 1) / 2 + GLS_MAXP;
+  __shared__ double part[4][NA];
+  const int sidx = order[blockIdx.x];
+  const SubsetDesc D = desc[sidx];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  double acc[NA];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) acc[e] = 0.0;
+  for (int r = tid; r < D.n; r += 256) {
+    double x[GLS_MAXP], wv[GLS_MAXP];
+#pragma unroll
+    for (int j = 0; j < GLS_MAXP; ++j) {
+      x[j] = j < p ? Xp[(int64_t)j * nP + D.offP + r] : 0.0;
+      wv[j] = j < p ? Wp[(int64_t)j * nP + D.offP + r] : 0.0;
+    }
+    const double a = alphabuf[D.offP + r];
+    int e = 0;
+#pragma unroll
+    for (int j = 0; j < GLS_MAXP; ++j) {
+#pragma unroll
+      for (int k = 0; k <= j; ++k, ++e) acc[e] = fma(x[j], wv[k], acc[e]);
+    }
+#pragma unroll
+    for (int j = 0; j < GLS_MAXP; ++j, ++e) acc[e] = fma(x[j], a, acc[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < NA; ++e) {
+    const double v = wsum64(acc[e]);
+    if (l == 0) part[w][e] = v;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double A[GLS_MAXP][GLS_MAXP], b[GLS_MAXP];
+  int e = 0;
+  for (int j = 0; j < GLS_MAXP; ++j)
+    for (int k = 0; k <= j; ++k, ++e) A[j][k] = (part[0][e] + part[1][e]) + (part[2][e] + part[3][e]);
+  for (int j = 0; j < GLS_MAXP; ++j, ++e) b[j] = (part[0][e] + part[1][e]) + (part[2][e] + part[3][e]);
+  // Cholesky of the p x p normal matrix, then two triangular solves
+  int bad = 0;
+  for (int j = 0; j < p; ++j) {
+    double d = A[j][j];
+    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+    if (!(d > 0.0)) {
+      bad = j + 1;
+      break;
+    }
+    d = sqrt(d);
+    A[j][j] = d;
+    for (int i = j + 1; i < p; ++i) {
+      double s = A[i][j];
+      for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k];
+      A[i][j] = s / d;
+    }
+  }
+  status[sidx] = bad;
+  if (bad) {
+    for (int j = 0; j < p; ++j) beta[(int64_t)sidx * p + j] = __builtin_nan("");
+    return;
+  }
+  for (int j = 0; j < p; ++j) {
+    double s = b[j];
+    for (int k = 0; k < j; ++k) s -= A[j][k] * b[k];
+    b[j] = s / A[j][j];
+  }
+  for (int j = p - 1; j >= 0; --j) {
+    double s = b[j];
+    for (int k = j + 1; k < p; ++k) s -= A[k][j] * b[k];
+    b[j] = s / A[j][j];
+  }
+  for (int j = 0; j < p; ++j) beta[(int64_t)sidx * p + j] = b[j];
+}
+
 // ------------------------------------------------------------- launchers --
 template <typename T>
 static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items, int max_npad, const T* Lbuf,
@@ -585,6 +674,14 @@ hipError_t launch_predict_val(const Launch& Lc, const int2* items, int n_items, 
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_predict_val, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, items, Lc.theta,
                      tx, ty, vx, vy, yV, alpha, yhat, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_gls(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n_items, int p,
+                      int64_t nP, const double* Xp, const double* Wp, const double* alpha, double* beta,
+                      int32_t* status) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gls, dim3(n_items), dim3(256), 0, s, desc, order, p, nP, Xp, Wp, alpha, beta, status);
   return hipGetLastError();
 }
 

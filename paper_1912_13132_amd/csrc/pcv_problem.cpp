@@ -243,6 +243,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     p->core_rect.assign(core_rect, core_rect + 4 * (size_t)S);
     build_router(p);
   }
+  p->train_ptr.assign(tptr, tptr + S + 1);
+  p->train_idx.assign(tidx, tidx + tptr[S]);
 
   int64_t offT = 0, offV = 0, offP = 0, offL = 0, offInv = 0, offPC = 0;
   std::vector<int32_t> act_ids, all_ids;
@@ -707,6 +709,56 @@ pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local) {
     if (status[i]) return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(i) + " is not positive definite in FP64");
   p->fact_theta = th[0];
   p->factored = true;
+  return PCV_OK;
+}
+
+pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta, int32_t* status_out) {
+  HIPCHK(hipSetDevice(p->device));
+  const int64_t nP = p->nP;
+  // covariates of every training membership, gathered into the padded layout
+  std::vector<double> Xp((size_t)ncov * nP, 0.0);
+  for (int32_t i = 0; i < p->S; ++i) {
+    const SubsetDesc& d = p->desc[i];
+    for (int64_t j = p->train_ptr[i], a = 0; j < p->train_ptr[i + 1]; ++j, ++a)
+      for (int c = 0; c < ncov; ++c) Xp[(size_t)c * nP + d.offP + a] = X[(int64_t)p->train_idx[j] * ncov + c];
+  }
+  double *d_X = nullptr, *d_W = nullptr, *d_beta = nullptr;
+  int32_t* d_st = nullptr;
+  const int count = (int)p->order_all.size();
+  Launch Lc{p->stream, p->d_desc_fact, p->d_theta_fact};
+  hipError_t e = hipMalloc((void**)&d_X, sizeof(double) * Xp.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&d_W, sizeof(double) * Xp.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&d_beta, sizeof(double) * (size_t)p->S * ncov);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_st, sizeof(int32_t) * p->S);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_X, Xp.data(), sizeof(double) * Xp.size(), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d_W, 0, sizeof(double) * Xp.size(), p->stream);
+  // W = M^{-1} X column by column through the resident FP64 factors
+  for (int c = 0; c < ncov && e == hipSuccess; ++c) {
+    e = launch_trsv_fwd_f64(Lc, p->d_order_all, count, p->max_npad, p->d_Lf, p->d_Invf, nullptr,
+                            d_X + (size_t)c * nP, p->d_zf, nullptr);
+    if (e == hipSuccess)
+      e = launch_trsv_bwd_f64(Lc, p->d_order_all, count, p->max_npad, p->d_Lf, p->d_Invf, p->d_zf,
+                              d_W + (size_t)c * nP, nullptr);
+  }
+  if (e == hipSuccess)
+    e = launch_gls(p->stream, p->d_desc_fact, p->d_order_all, count, ncov, nP, d_X, d_W, p->d_alpha_fact, d_beta,
+                   d_st);
+  std::vector<double> hb((size_t)p->S * ncov);
+  std::vector<int32_t> hs(p->S);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hb.data(), d_beta, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), d_st, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  for (void* b : {(void*)d_X, (void*)d_W, (void*)d_beta, (void*)d_st}) (void)hipFree(b);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE, std::string("gls: ") + hipGetErrorString(e));
+  // subsets without training points have no estimate
+  std::vector<char> has(p->S, 0);
+  for (int32_t i : p->order_all) has[i] = 1;
+  for (int32_t i = 0; i < p->S; ++i) {
+    for (int c = 0; c < ncov; ++c) beta[(int64_t)i * ncov + c] = has[i] ? hb[(size_t)i * ncov + c] : __builtin_nan("");
+    if (status_out) status_out[i] = has[i] ? hs[i] : -1;
+  }
   return PCV_OK;
 }
 

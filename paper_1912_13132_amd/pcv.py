@@ -93,6 +93,7 @@ def lib():
     L.pcv_eval_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p]
     L.pcv_factor.argtypes = [P, ctypes.POINTER(Theta)]
     L.pcv_factor_local.argtypes = [P, ctypes.POINTER(Theta)]
+    L.pcv_gls.argtypes = [P, ctypes.c_int32, _c_double_p, _c_double_p, _c_int32_p]
     L.pcv_eval_grid.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p, _c_double_p,
                                 _c_int32_p]
     L.pcv_predict.argtypes = [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
@@ -114,7 +115,7 @@ def lib():
     L.pcv_last_error.restype = ctypes.c_char_p
     for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
               "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create", "pcv_factor_local",
-              "pcv_eval_grid",
+              "pcv_eval_grid", "pcv_gls",
               "pcv_server_submit_predict", "pcv_server_submit_eval", "pcv_server_wait",
               "pcv_server_stats", "pcv_server_report_get", "pcv_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
@@ -258,6 +259,19 @@ class Problem:
                                  None if var is None else _ptr(var, ctypes.c_double),
                                  1 if obs_noise else 0, _ptr(owner, ctypes.c_int32)))
         return mean, var, owner
+
+    def gls(self, X):
+        """GLS mean coefficients [S][p] per subset from covariates X [n][p]
+        (Sec. 5, eq. (8)), through the resident factors; also the status."""
+        X = _as(X, np.float64)
+        if X.ndim == 1:
+            X = X[:, None]
+        X = np.ascontiguousarray(X)
+        beta = np.zeros((self.S, X.shape[1]))
+        st = np.zeros(self.S, dtype=np.int32)
+        _check(lib().pcv_gls(self._handle(), X.shape[1], _ptr(X, ctypes.c_double),
+                             _ptr(beta, ctypes.c_double), _ptr(st, ctypes.c_int32)))
+        return beta, st
 
     def info(self):
         S = ctypes.c_int32()

@@ -96,3 +96,28 @@ def test_local_theta_factorisation_predicts_with_each_subsets_theta(w_small):
                                 sigma2=1.2)
         np.testing.assert_allclose(mean[sel], mo, rtol=1e-9, atol=1e-10)
         np.testing.assert_allclose(var[sel], vo, rtol=1e-9, atol=1e-10)
+
+
+@pytest.mark.parametrize("local", [False, True])
+def test_gls_coefficients_per_subset(w_small, local):
+    """eq. (8) per subset with an intercept, the coordinates and their
+    product as covariates, through the resident factors (global or local
+    theta), against the oracle."""
+    pt = w_small.part
+    S = pt.n_subsets
+    X = np.c_[np.ones(len(w_small.y)), w_small.locs, w_small.locs[:, 0] * w_small.locs[:, 1]]
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 801]))
+    loc_th = [(0.05 * 2 ** r.uniform(-1, 1), 0.1 * 2 ** r.uniform(-1, 1)) for _ in range(S)]
+    say(f"[case] GLS local={local}")
+    with pcv.Problem.from_workload(w_small, prec="mixed") as P:
+        if local:
+            P.factor_local([pcv.theta(a, b) for a, b in loc_th])
+        else:
+            P.factor(pcv.theta(0.05, 0.1))
+        beta, st = P.gls(X)
+    for i in range(S):
+        T = pt.train_idx[pt.train_ptr[i]:pt.train_ptr[i + 1]]
+        th, lam = loc_th[i] if local else (0.05, 0.1)
+        ref = oracle.gls_beta_subset(w_small.locs[T], w_small.y[T], X[T], 0, th, lam)
+        assert st[i] == 0
+        np.testing.assert_allclose(beta[i], ref, rtol=1e-8, atol=1e-9)

@@ -240,6 +240,22 @@ def test_gls_reduces_to_ols_without_correlation():
     np.testing.assert_allclose(beta, ols, rtol=1e-12)
 
 
+def test_gls_recovers_an_exact_mean_and_is_equivariant():
+    """eq. (8) is a projection: y = X b0 gives beta = b0 for any covariance,
+    and y -> y + X g shifts beta by g (a swapped operand or a missing inverse
+    breaks both)."""
+    r = _rng(13)
+    sT = r.uniform(0, 1, (60, 2))
+    X = np.c_[np.ones(60), sT, sT[:, 0] * sT[:, 1]]
+    b0 = np.array([0.7, -1.3, 2.0, 0.4])
+    np.testing.assert_allclose(oracle.gls_beta_subset(sT, X @ b0, X, COV_EXP, 0.3, 0.05), b0, rtol=1e-9)
+    y = r.standard_normal(60)
+    g = np.array([1.0, 2.0, -3.0, 0.5])
+    b1 = oracle.gls_beta_subset(sT, y, X, COV_EXP, 0.3, 0.05)
+    b2 = oracle.gls_beta_subset(sT, y + X @ g, X, COV_EXP, 0.3, 0.05)
+    np.testing.assert_allclose(b2 - b1, g, rtol=1e-8, atol=1e-9)
+
+
 def test_likelihood_against_scipy_density():
     """eq. (2) equals -2 log N(y; 0, sigma^2 Sigma + tau I), tau = lambda sigma^2."""
     r = _rng(12)
