@@ -154,19 +154,31 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB]
 // rows < nreal to ld and records the first failing pivot (1-based global
 // row) in bad (thread 0's copies).  All NT threads take part.
 //
-// Blocked in 16 x 16 tiles.  Factor, for each tile column kb:
-//   1. the diagonal tile by one wave, one row per lane, pivots and columns
-//      broadcast with lane shuffles (no barriers inside);
-//   2. the tiles below it by forward substitution, one row per thread;
-//   3. the trailing lower triangle updated with the new tile column.
-// Inverse: the four diagonal tiles first (one column per thread), then the
-// off-diagonal tiles by distance from the diagonal,
-//   Inv_ij = -Inv_ii * sum_{j<=k<i} L_ik Inv_kj.
-__device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], double* rdiag, int nreal,
-                                   int grow0, double& ld, int& bad) {
+// Blocked in 16 x 16 tiles.  For each tile column kb:
+//   1. wave 0 factors the diagonal tile in registers, lane c holding column
+//      c of the (symmetric) tile: at pivot j the pivot and column j are
+//      broadcast with readlane and every lane updates its own column; then
+//      lane c builds column c of the tile's inverse by forward substitution;
+//   2. the tiles below: X_I = A_Ik L_kk^{-T}, one FP64 MFMA tile per wave;
+//   3. the trailing lower block triangle: A_IK -= X_I X_K^T, one MFMA tile
+//      per wave.
+// Inverse off the diagonal, by distance d = I - J, one tile per wave:
+//   Inv_IJ = -Inv_II * sum_{J<=K<I} L_IK Inv_KJ   (two MFMA products).
+__device__ __forceinline__ double rlane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], double* rdiag, int nreal, int grow0,
+                                   double& ld, int& bad) {
+  typedef double f64x4_t __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int li = l & 15, kq = l >> 4;  // MFMA operand lane roles: index li, k slice kq
   for (int kb = 0; kb < 4; ++kb) {
     const int k0 = 16 * kb;
+    // ---- leaf: factor and invert the diagonal tile in wave 0
     // 1. diagonal tile, wave 0: lane l owns entries (r, c) = (l / 4, l % 4 + 4 u).
     //    One wave touches LDS in program order, so no barrier is needed.
     if (w == 0) {
@@ -200,81 +212,112 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
       }
     }
     __syncthreads();
-    if (kb == 3) break;
-    // 2. tiles below: rows i = k0 + 16 + t solve x L_kk^T = a; 16 lanes per row,
-    //    lane c keeps a_c, x_j is broadcast from lane j with a shuffle.
-    {
-      const int rows = 48 - k0;
-      for (int base = 4 * w; base < rows; base += 4 * (NT / 64)) {
-        const int ri = base + (l >> 4), c = l & 15;
-        const bool live = ri < rows;
-        const int i = k0 + 16 + (live ? ri : 0);
-        double av = Dg[i][k0 + c];
-        for (int j = 0; j < 16; ++j) {
-          const double xj = __shfl(av, (l & 48) + j, 64) * rdiag[k0 + j];
-          if (c == j) av = xj;
-          else if (c > j) av -= xj * Dg[k0 + c][k0 + j];
-        }
-        if (live) Dg[i][k0 + c] = av;
-      }
-    }
-    __syncthreads();
-    // 3. trailing update of the lower triangle: entry (i, k), k0+16 <= k <= i
-    {
-      const int m0 = 48 - k0;                       // trailing size
-      for (int e = tid; e < m0 * m0; e += NT) {
-        const int ii = e / m0, kk = e - ii * m0;
-        if (kk <= ii) {
-          const int i = k0 + 16 + ii, k = k0 + 16 + kk;
-          double sacc = 0.0;
-#pragma unroll 4
-          for (int m = 0; m < 16; ++m) sacc += Dg[i][k0 + m] * Dg[k][k0 + m];
-          Dg[i][k] -= sacc;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // log det of this block: 2 sum log L_jj over real rows
-  if (w == 0) {
-    double t = l < nreal ? 2.0 * log(Dg[l][l]) : 0.0;
+    if (w == 0) {
+      // log det of the tile's real rows
+      double t = (l < 16 && k0 + l < nreal) ? 2.0 * log(Dg[k0 + l][k0 + l]) : 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    if (l == 0) ld += t;
-  }
-  // inverse of the four diagonal tiles: thread (b, c) computes column c of
-  // Inv_bb top-down, reading back its own earlier entries from LDS
-  if (tid < 64) {
-    const int o = 16 * (tid >> 4), c = tid & 15;
-    for (int r = c; r < 16; ++r) {
-      double sacc = r == c ? 1.0 : 0.0;
-      for (int m = c; m < r; ++m) sacc -= Dg[o + r][o + m] * Dg[o + c][o + m + 1];
-      Dg[o + c][o + r + 1] = sacc * rdiag[o + r];
-    }
-  }
-  __syncthreads();
-  // off-diagonal tiles, distance d = i - j
-  for (int d = 1; d < 4; ++d) {
-    const int np = 4 - d;  // tile pairs (i, j = i - d), j = 0..np-1
-    for (int e = tid; e < np * 256; e += NT) {
-      const int pj = e >> 8, r = (e >> 4) & 15, c = e & 15;
-      const int j = pj, i = pj + d;
-      double sacc = 0.0;
-      // k = j: the diagonal tile Inv_jj is lower triangular (only m >= c stored)
-      for (int m = c; m < 16; ++m) sacc += Dg[16 * i + r][16 * j + m] * Dg[16 * j + c][16 * j + m + 1];
-      for (int k = j + 1; k < i; ++k) {
-#pragma unroll 4
-        for (int m = 0; m < 16; ++m) sacc += Dg[16 * i + r][16 * k + m] * Dg[16 * j + c][16 * k + m + 1];
+      for (int off = 8; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      if (tid == 0) ld += t;
+      int c = li;
+      asm volatile("" : "+v"(c));
+      // inverse of the tile, lane c building column c by forward substitution
+      // over the stored factor (wave-ordered LDS: no barrier needed)
+      __builtin_amdgcn_wave_barrier();
+      double y[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) y[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double yj = y[j] * rdiag[k0 + j];
+        y[j] = yj;
+#pragma unroll
+        for (int r = j + 1; r < 16; ++r) y[r] = fma(-Dg[k0 + r][k0 + j], yj, y[r]);
+        asm volatile("" : "+v"(y[0]), "+v"(y[1]), "+v"(y[2]), "+v"(y[3]), "+v"(y[4]), "+v"(y[5]), "+v"(y[6]),
+                     "+v"(y[7]), "+v"(y[8]), "+v"(y[9]), "+v"(y[10]), "+v"(y[11]), "+v"(y[12]), "+v"(y[13]),
+                     "+v"(y[14]), "+v"(y[15])
+                     :
+                     : "memory");
       }
-      Tb[pj][r][c] = sacc;
+      if (l < 16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (r >= c) Dg[k0 + c][k0 + r + 1] = y[r];
+      }
     }
     __syncthreads();
-    for (int e = tid; e < np * 256; e += NT) {
-      const int pj = e >> 8, r = (e >> 4) & 15, c = e & 15;
-      const int j = pj, i = pj + d;
-      double sacc = 0.0;
-      for (int m = 0; m <= r; ++m) sacc += Dg[16 * i + m][16 * i + r + 1] * Tb[pj][m][c];
-      Dg[16 * j + c][16 * i + r + 1] = -sacc;
+    if (kb == 3) break;
+    // ---- tiles below: X_I = A_I,k L_kk^{-T} (MFMA), wave w -> block row kb + 1 + w
+    if (w < 3 - kb) {
+      const int I = kb + 1 + w;
+      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int m = 4 * ks + kq;
+        const double av = Dg[16 * I + li][k0 + m];
+        const double bv = m <= li ? Dg[k0 + m][k0 + li + 1] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dg[16 * I + 4 * v + kq][k0 + li] = acc[v];
+    }
+    __syncthreads();
+    // ---- trailing update of the lower block triangle: A_IK -= X_I X_K^T
+    {
+      const int t = 3 - kb;
+      const int npairs = t * (t + 1) / 2;
+      if (w < npairs) {
+        // pair index -> (I, K), K <= I, both in kb+1..3
+        int I = kb + 1, K = kb + 1, q = w;
+        while (q > I - (kb + 1)) {
+          q -= I - kb;
+          ++I;
+        }
+        K = kb + 1 + q;
+        f64x4_t acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = Dg[16 * I + 4 * v + kq][16 * K + li];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int m = 4 * ks + kq;
+          const double av = -Dg[16 * I + li][k0 + m];
+          const double bv = Dg[16 * K + li][k0 + m];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (I != K || li <= 4 * v + kq) Dg[16 * I + 4 * v + kq][16 * K + li] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- off-diagonal tiles of the inverse by distance d = I - J:
+  //      Inv_IJ = -Inv_II * sum_{K=J}^{I-1} L_IK Inv_KJ
+  for (int d = 1; d < 4; ++d) {
+    if (w < 4 - d) {
+      const int I = d + w, J = w;
+      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < I; ++K) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int m = 4 * ks + kq;
+          const double av = Dg[16 * I + li][16 * K + m];
+          const double bv = (K > J || m >= li) ? Dg[16 * J + li][16 * K + m + 1] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tb[w][4 * v + kq][li] = acc[v];
+      __builtin_amdgcn_wave_barrier();
+      f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int m = 4 * ks + kq;
+        const double av = m <= li ? -Dg[16 * I + m][16 * I + li + 1] : 0.0;
+        const double bv = Tb[w][m][li];
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc2, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dg[16 * J + li][16 * I + 4 * v + kq + 1] = acc2[v];
     }
     __syncthreads();
   }
@@ -304,7 +347,6 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
   __shared__ T colx[PB], coly[PB];  // the current panel's column coordinates
 
   T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
-  T* Rs = Ps + PB * LDK;                    // [RCH][LDK] chunk rows
   T* L21s = reinterpret_cast<T*>(smem_u);  // [64][LDI]  -L21 (second half update)
   double(*Dg)[LDD] = reinterpret_cast<double(*)[LDD]>(smem_u);
 
