@@ -117,7 +117,7 @@ __device__ __forceinline__ void stage_inv(double (*IL)[65], const double* __rest
 }
 
 template <typename T, int MR>
-__global__ __launch_bounds__(512, 1) void k_trsv_fwd(const SubsetDesc* __restrict__ desc,
+__global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_trsv_fwd(const SubsetDesc* __restrict__ desc,
                                                      const int32_t* __restrict__ order,
                                                      const T* __restrict__ Lbuf,
                                                      const double* __restrict__ Invbuf,
@@ -168,15 +168,21 @@ __global__ __launch_bounds__(512, 1) void k_trsv_fwd(const SubsetDesc* __restric
       const int row = tid + SNT * i;
       if (row >= c0 + TB && row < npad) {
         const vec_t* Lr = reinterpret_cast<const vec_t*>(L + packed_rowoff32(row) + c0);
-        vec_t v[TB / VW];
-#pragma unroll
-        for (int k = 0; k < TB / VW; ++k) v[k] = Lr[k];
         double acc = 0.0;
+        // the 64-column segment in 128-byte parts (bounds the vectors in flight)
+        constexpr int NH = sizeof(T) == 8 ? 4 : 2;
 #pragma unroll
-        for (int k = 0; k < TB / VW; ++k) {
-          const T* e = reinterpret_cast<const T*>(&v[k]);
+        for (int h = 0; h < NH; ++h) {
+          constexpr int NV = TB / VW / NH;
+          vec_t v[NV];
 #pragma unroll
-          for (int u = 0; u < VW; ++u) acc += (double)e[u] * zJ[k * VW + u];
+          for (int k = 0; k < NV; ++k) v[k] = Lr[h * NV + k];
+#pragma unroll
+          for (int k = 0; k < NV; ++k) {
+            const T* e = reinterpret_cast<const T*>(&v[k]);
+#pragma unroll
+            for (int u = 0; u < VW; ++u) acc += (double)e[u] * zJ[(h * NV + k) * VW + u];
+          }
         }
         t[i] -= acc;
       }
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(512, 1) void k_trsv_fwd(const SubsetDesc* __restric
 }
 
 template <typename T, int MQ>
-__global__ __launch_bounds__(512, 1) void k_trsv_bwd(const SubsetDesc* __restrict__ desc,
+__global__ __launch_bounds__(512, MQ <= 2 ? 4 : 2) void k_trsv_bwd(const SubsetDesc* __restrict__ desc,
                                                      const int32_t* __restrict__ order,
                                                      const T* __restrict__ Lbuf,
                                                      const double* __restrict__ Invbuf,
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(512, 1) void k_trsv_bwd(const SubsetDesc* __restric
       const int c = 4 * (tid + SNT * i);
       if (c < c0) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 16
+#pragma unroll 8
         for (int r = 0; r < TB; ++r) {
           const q_t v = *reinterpret_cast<const q_t*>(L + packed_rowoff32(c0 + r) + c);
           const double xr = xJ[r];
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(512, 1) void k_trsv_bwd(const SubsetDesc* __restric
 // sums for block J, written to a partial buffer).  A second kernel adds the
 // partials in a fixed order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void k_residual_tiles(const SubsetDesc* __restrict__ desc,
+__global__ __launch_bounds__(256, 3) void k_residual_tiles(const SubsetDesc* __restrict__ desc,
                                                         const int2* __restrict__ items,
                                                         const ThetaDev* __restrict__ theta,
                                                         const double* __restrict__ tx,
@@ -324,7 +330,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_tiles(const SubsetDesc* __r
 #pragma unroll
     for (int u = 0; u < 8; ++u) rp[u] = cp[u] = 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 8; ++u) {
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const double dx = xi[u] - xj[v], dy = yi[u] - yj[v];
@@ -333,6 +339,10 @@ __global__ __launch_bounds__(256, 2) void k_residual_tiles(const SubsetDesc* __r
         rp[u] += c * aj[v];
         cp[v] += c * ai[u];
       }
+      // one sub-tile row at a time: bounds the exponentials in flight
+      asm volatile("" : "+v"(rp[u]), "+v"(cp[0]), "+v"(cp[1]), "+v"(cp[2]), "+v"(cp[3]), "+v"(cp[4]),
+                   "+v"(cp[5]), "+v"(cp[6]), "+v"(cp[7]));
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       double t = rp[u];
