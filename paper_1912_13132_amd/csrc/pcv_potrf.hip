@@ -65,9 +65,12 @@ struct Cfg<double> {
 // Correlation of Sec. 3 (exponential) or Matern-3/2.  Padding points carry
 // infinite coordinates: their distance to anything is inf or NaN, and the
 // entry is then exactly 0.
+// The FP32 tiles only feed the factor that preconditions the FP64
+// refinement (whose residual uses the exact FP64 covariance), so the
+// hardware exp2 and square root (about 1 ulp) are used here.
 __device__ __forceinline__ float corr_t(int cov, float d, float ir) {
   const float t = d * ir;
-  const float e = expf(-t);
+  const float e = __builtin_amdgcn_exp2f(-1.44269504088896341f * t);
   const float c = cov == 1 ? (1.0f + t) * e : e;
   return d < INFINITY ? c : 0.0f;
 }
@@ -77,6 +80,9 @@ __device__ __forceinline__ double corr_t(int cov, double d, double ir) {
   const double c = cov == 1 ? (1.0 + t) * e : e;
   return d < INFINITY ? c : 0.0;
 }
+
+__device__ __forceinline__ float fsqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt_t(double x) { return sqrt(x); }
 
 // The four accumulator-row entries crow(g, 0..3) of a 16-wide LDS row segment.
 __device__ __forceinline__ void load_crow4(const float* row, int g, float (&a)[4]) {
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
 #pragma unroll
             for (int bj = 0; bj < NBJ; ++bj) {
               const T dx = xr[bj] - xc, dy = yr[bj] - yc;
-              tv[bj][v] = corr_t(cov, sqrt(dx * dx + dy * dy), ir);
+              tv[bj][v] = corr_t(cov, fsqrt_t(dx * dx + dy * dy), ir);
             }
           }
 #pragma unroll
