@@ -158,10 +158,21 @@ pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs,
 pcv_status pcv_eval(pcv_problem* p, const pcv_theta* theta, double* loss,
                     pcv_eval_report* report);
 
-/* n_theta evaluations; losses[k] for thetas[k].  Equivalent to n_theta calls
- * of pcv_eval. */
+/* n_theta evaluations; losses[k] for thetas[k], bit-identical to n_theta
+ * calls of pcv_eval.  Up to 64 theta values run together, one launch per
+ * kernel over all (theta, subset) pairs (the per-theta workspace is sized
+ * from the memory cap, else at most 16 GiB; when one slot does not fit twice,
+ * the values run one by one).  A theta whose subsets need the FP64 re-run
+ * is evaluated again on its own. */
 pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas,
                           double* losses);
+
+/* As pcv_eval_batch; report (may be NULL) receives the wall time, the phase
+ * times summed over the launches (when profiling), n_val, n_subsets_used and
+ * in n_fallback_fp64 the number of theta values evaluated again on their own.
+ * The per-subset arrays of the report are not written. */
+pcv_status pcv_eval_batch_ex(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas,
+                             double* losses, pcv_eval_report* report);
 
 /* Local losses over a set of theta values (Sec. 4.4: local RMSPE and the
  * best local zeta of each subset, the basis of non-stationary fits).

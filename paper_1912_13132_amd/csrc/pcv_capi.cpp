@@ -164,11 +164,19 @@ pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thet
     pcv_status s = check_theta(&thetas[k]);
     if (s != PCV_OK) return fail(s, "theta[" + std::to_string(k) + "]: " + pcv::g_err);
   }
+  return pcv::eval_batch_impl(p, n_theta, thetas, losses, nullptr);
+}
+
+pcv_status pcv_eval_batch_ex(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,
+                             pcv_eval_report* report) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (n_theta < 0 || (n_theta > 0 && (!thetas || !losses))) return fail(PCV_ERR_INVALID, "bad batch arguments");
   for (int32_t k = 0; k < n_theta; ++k) {
-    pcv_status s = pcv::eval_impl(p, thetas[k], &losses[k], nullptr);
-    if (s != PCV_OK) return s;
+    pcv_status s = check_theta(&thetas[k]);
+    if (s != PCV_OK) return fail(s, "theta[" + std::to_string(k) + "]: " + pcv::g_err);
   }
-  return PCV_OK;
+  return pcv::eval_batch_impl(p, n_theta, thetas, losses, report);
 }
 
 pcv_status pcv_eval_grid(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,

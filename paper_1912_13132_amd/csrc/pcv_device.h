@@ -25,8 +25,14 @@ struct SubsetDesc {
   int64_t offL;    // packed tile-row lower factor                 [packed_size(npad)]
   int64_t offInv;  // inverse diagonal blocks, FP64                [npad * TB]
   int64_t offPC;   // residual column partials, FP64               [TB * nb (nb - 1) / 2]
+  int64_t offX;    // padded factorisation coordinates            [npad]
+  int64_t offE;    // validation predictions / squared errors     [m]
   int32_t n, m, npad;
   int32_t th;      // theta slot: kernels read theta[th]
+  // Several theta values are evaluated in one launch by replicating the
+  // descriptors per theta slot: the per-theta workspace offsets (offP, offL,
+  // offInv, offPC, offE) move to that slot's copy of the buffers, the input
+  // offsets (offT, offV, offX) stay.
 };
 
 // The evaluated parameters, read by every kernel from device memory so that
@@ -126,9 +132,11 @@ hipError_t launch_gls(hipStream_t s, const SubsetDesc* desc, const int32_t* orde
 hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n_items,
                        const double* yT, const double* alpha, double* quad);
 // Per-subset SSPE and the global loss (fixed-order compensated sums), count
-// of subsets with nonzero status.  With rhs2 non-null, an active subset with
-// rhs2[i] > tol^2 * ynorm2[i] gets status PCV_STATUS_STAGNATED first.
-hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, const double* err,
+// of subsets with nonzero status, for n_theta theta slots of S descriptors
+// each (slot t: descriptors t S .. t S + S - 1, outputs out_total[t],
+// out_nbad[t]).  With rhs2 non-null, an active subset with
+// rhs2 > tol^2 * ynorm2 gets status PCV_STATUS_STAGNATED first.
+hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_theta, const double* err,
                          int32_t* status, const int32_t* active, const double* rhs2,
                          const double* ynorm2, double tol, double* per_subset_sspe,
                          double* out_total, int32_t* out_nbad);

@@ -17,6 +17,32 @@ struct pcv_router {
   std::vector<int32_t> ptr, list;  // CSR: cores touching bucket b
 };
 
+// Workspace for evaluating several theta values in one launch per kernel:
+// B theta slots, the descriptors replicated per slot (see SubsetDesc), and
+// per group size nb <= B the item lists over (slot, subset) pairs and the
+// captured graph.
+struct pcv_batch_plan {
+  int nb = 0;
+  int32_t* d_order = nullptr;
+  int2 *d_row_items = nullptr, *d_tile_items = nullptr, *d_val_items = nullptr;
+  int n_order = 0, n_row = 0, n_tile = 0, n_val = 0;
+  hipGraphExec_t graph = nullptr;
+};
+struct pcv_batch {
+  int B = 0;
+  pcv::SubsetDesc* d_desc = nullptr;
+  void* d_L = nullptr;  // FP32 (mixed) or FP64 factors, B copies
+  double *d_Inv = nullptr, *d_z = nullptr, *d_x = nullptr, *d_alpha = nullptr, *d_r = nullptr;
+  double *d_rrow = nullptr, *d_pcol = nullptr, *d_rhs2 = nullptr, *d_yhat = nullptr, *d_err = nullptr;
+  double *d_logdet = nullptr, *d_sspe = nullptr, *d_quad = nullptr, *d_total = nullptr;
+  int32_t *d_status = nullptr, *d_nbad = nullptr;
+  pcv::ThetaDev* d_theta = nullptr;
+  pcv::ThetaDev* h_theta = nullptr;  // pinned [B]
+  double* h_total = nullptr;         // pinned [B]
+  int32_t* h_nbad = nullptr;         // pinned [B]
+  pcv_batch_plan plans[2];
+};
+
 struct pcv_problem {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -95,6 +121,8 @@ struct pcv_problem {
 
   bool factored = false;
   pcv_theta fact_theta{};
+
+  pcv_batch batch;
 };
 
 namespace pcv {
@@ -105,6 +133,9 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
                          const int32_t* val_idx, const double* core_rect);
 void problem_free(pcv_problem* p);
 pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep);
+// n_theta evaluations, batched B at a time when the workspace allows.
+pcv_status eval_batch_impl(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,
+                           pcv_eval_report* rep);
 pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local);
 pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta, int32_t* status);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,

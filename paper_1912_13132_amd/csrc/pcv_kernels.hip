@@ -434,8 +434,8 @@ __global__ __launch_bounds__(256) void k_predict_val(const SubsetDesc* __restric
   if (q == 0 && v < m) {
     const double p = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
     const double e = p - yV[D.offV + v];
-    yhat[D.offV + v] = p;
-    err[D.offV + v] = e * e;
+    yhat[D.offE + v] = p;
+    err[D.offE + v] = e * e;
   }
 }
 
@@ -464,25 +464,27 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
   __shared__ double hi[256], lo[256];
   __shared__ int nb[256];
   const int tid = threadIdx.x;
+  const int base = blockIdx.x * S;  // this theta slot's descriptors
   double th = 0.0, tl = 0.0;
   int bad = 0;
   for (int i = tid; i < S; i += 256) {
-    const SubsetDesc D = desc[i];
+    const int k = base + i;
+    const SubsetDesc D = desc[k];
     double zi = 0.0, zc = 0.0;
     if (active[i]) {
       for (int v = 0; v < D.m; ++v) {
         double s, e;
-        two_sum(zi, err[D.offV + v], s, e);
+        two_sum(zi, err[D.offE + v], s, e);
         zi = s;
         zc += e;
       }
       // a mixed-precision subset whose residual before the last correction
       // was not small enough is re-run in FP64 like a broken-down one
-      if (rhs2 && status[i] == 0 && rhs2[i] > tol2 * ynorm2[i]) status[i] = PCV_STATUS_STAGNATED;
-      if (status[i]) ++bad;
+      if (rhs2 && status[k] == 0 && rhs2[k] > tol2 * ynorm2[i]) status[k] = PCV_STATUS_STAGNATED;
+      if (status[k]) ++bad;
     }
     const double z = zi + zc;
-    per_subset[i] = z;
+    per_subset[k] = z;
     double s, e;
     two_sum(th, z, s, e);
     th = s;
@@ -503,8 +505,8 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
     __syncthreads();
   }
   if (tid == 0) {
-    out_total[0] = hi[0] + lo[0];
-    out_nbad[0] = nb[0];
+    out_total[blockIdx.x] = hi[0] + lo[0];
+    out_nbad[blockIdx.x] = nb[0];
   }
 }
 
@@ -702,11 +704,11 @@ hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* ord
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, const double* err,
+hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_theta, const double* err,
                          int32_t* status, const int32_t* active, const double* rhs2,
                          const double* ynorm2, double tol, double* per_subset, double* out_total,
                          int32_t* out_nbad) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, desc, S, err, status, active, rhs2, ynorm2,
+  hipLaunchKernelGGL(k_reduce, dim3(n_theta), dim3(256), 0, s, desc, S, err, status, active, rhs2, ynorm2,
                      tol * tol, per_subset, out_total, out_nbad);
   return hipGetLastError();
 }

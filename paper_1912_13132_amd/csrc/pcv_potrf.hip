@@ -361,8 +361,8 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
   const int n = D.n, npad = D.npad;
   T* __restrict__ L = Lbuf + D.offL;
   double* __restrict__ Inv = Invbuf + D.offInv;
-  const T* __restrict__ X = cx + D.offP;  // padded coordinates (npad entries)
-  const T* __restrict__ Y = cy + D.offP;
+  const T* __restrict__ X = cx + D.offX;  // padded coordinates (npad entries)
+  const T* __restrict__ Y = cy + D.offX;
   const int cov = theta[D.th].cov;
   const T ir = (T)theta[D.th].inv_range;
   const double lam64 = theta[D.th].lambda;

@@ -260,6 +260,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     d.offL = offL;
     d.offInv = offInv;
     d.offPC = offPC;
+    d.offX = offP;
+    d.offE = offV;
     offT += d.n;
     offV += d.m;
     offP += d.npad;
@@ -400,6 +402,11 @@ void problem_free(pcv_problem* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   for (auto& g : p->graph_exec)
     if (g) (void)hipGraphExecDestroy(g);
+  for (auto& pl : p->batch.plans)
+    if (pl.graph) (void)hipGraphExecDestroy(pl.graph);
+  if (p->batch.h_theta) (void)hipHostFree(p->batch.h_theta);
+  if (p->batch.h_total) (void)hipHostFree(p->batch.h_total);
+  if (p->batch.h_nbad) (void)hipHostFree(p->batch.h_nbad);
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
   if (p->h_theta) (void)hipHostFree(p->h_theta);
@@ -480,7 +487,7 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
       HIPCHK(launch_quad(st, p->d_desc, p->d_order_eval, p->n_active, p->d_yT, p->d_alpha, p->d_quad));
       break;
     case 5:
-      HIPCHK(launch_reduce(st, p->d_desc, p->S, p->d_err, p->d_status, p->d_active,
+      HIPCHK(launch_reduce(st, p->d_desc, p->S, 1, p->d_err, p->d_status, p->d_active,
                            sweeps > 0 ? p->d_rhs2 : nullptr, p->d_ynorm2, p->opt.refine_tol, p->d_sspe,
                            p->d_total, p->d_nbad));
       break;
@@ -590,7 +597,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
       HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
                                 p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
       HIPCHK(launch_quad(p->stream, p->d_desc, p->d_order_eval, p->n_active, p->d_yT, p->d_alpha, p->d_quad));
-      HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, p->d_err, p->d_status, p->d_active, nullptr,
+      HIPCHK(launch_reduce(p->stream, p->d_desc, p->S, 1, p->d_err, p->d_status, p->d_active, nullptr,
                            nullptr, 0.0, p->d_sspe, p->d_total, p->d_nbad));
       HIPCHK(hipMemcpyAsync(p->h_total, p->d_total, sizeof(double), hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipMemcpyAsync(p->h_nbad, p->d_nbad, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
@@ -664,6 +671,265 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     }
     rep->seconds = now_s() - t0;
   }
+  return PCV_OK;
+}
+
+namespace {
+
+// Device bytes of one theta slot of the batch workspace.
+size_t batch_slot_bytes(const pcv_problem* p, bool mixed) {
+  return (size_t)p->nL * (mixed ? 4 : 8) + (size_t)p->nInv * 8 + (size_t)p->nP * 8 * 6 +
+         (size_t)p->nPC * 8 + (size_t)p->nnzV * 8 * 2 + (size_t)p->S * (8 * 4 + 4 + sizeof(SubsetDesc)) + 64;
+}
+
+pcv_status ensure_batch(pcv_problem* p, int B, bool mixed) {
+  pcv_batch& b = p->batch;
+  if (b.B >= B) return PCV_OK;
+  if (b.B > 0) return fail(PCV_ERR_STATE, "batch workspace already sized");
+  const int S = p->S;
+  pcv_status s;
+#define TRYB(x)              \
+  do {                       \
+    s = (x);                 \
+    if (s != PCV_OK) return s; \
+  } while (0)
+  std::vector<SubsetDesc> db((size_t)B * S);
+  for (int t = 0; t < B; ++t)
+    for (int i = 0; i < S; ++i) {
+      SubsetDesc d = p->desc[i];
+      d.th = t;
+      d.offP += (int64_t)t * p->nP;
+      d.offL += (int64_t)t * p->nL;
+      d.offInv += (int64_t)t * p->nInv;
+      d.offPC += (int64_t)t * p->nPC;
+      d.offE += (int64_t)t * p->nnzV;
+      db[(size_t)t * S + i] = d;
+    }
+  TRYB(upload(p, &b.d_desc, db));
+  if (mixed) {
+    float* L = nullptr;
+    TRYB(dalloc(p, &L, (size_t)B * p->nL));
+    b.d_L = L;
+  } else {
+    double* L = nullptr;
+    TRYB(dalloc(p, &L, (size_t)B * p->nL));
+    b.d_L = L;
+  }
+  TRYB(dalloc(p, &b.d_Inv, (size_t)B * p->nInv));
+  for (double** q : {&b.d_z, &b.d_x, &b.d_alpha, &b.d_r, &b.d_rrow}) TRYB(dalloc(p, q, (size_t)B * p->nP));
+  TRYB(dalloc(p, &b.d_pcol, (size_t)B * std::max<int64_t>(p->nPC, 1)));
+  TRYB(dalloc(p, &b.d_yhat, (size_t)B * std::max<int64_t>(p->nnzV, 1)));
+  TRYB(dalloc(p, &b.d_err, (size_t)B * std::max<int64_t>(p->nnzV, 1)));
+  for (double** q : {&b.d_rhs2, &b.d_logdet, &b.d_sspe, &b.d_quad}) TRYB(dalloc(p, q, (size_t)B * S));
+  TRYB(dalloc(p, &b.d_status, (size_t)B * S));
+  TRYB(dalloc(p, &b.d_total, (size_t)B));
+  TRYB(dalloc(p, &b.d_nbad, (size_t)B));
+  TRYB(dalloc(p, &b.d_theta, (size_t)B));
+#undef TRYB
+  HIPCHK(hipHostMalloc((void**)&b.h_theta, sizeof(ThetaDev) * B, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&b.h_total, sizeof(double) * B, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&b.h_nbad, sizeof(int32_t) * B, hipHostMallocDefault));
+  b.B = B;
+  return PCV_OK;
+}
+
+// Item lists over (slot, subset) pairs for the first nb slots, largest
+// subsets first (slots of one subset adjacent).
+pcv_status batch_plan(pcv_problem* p, int nb, pcv_batch_plan** out) {
+  pcv_batch& b = p->batch;
+  for (auto& pl : b.plans)
+    if (pl.nb == nb) {
+      *out = &pl;
+      return PCV_OK;
+    }
+  pcv_batch_plan* pl = nullptr;
+  for (auto& q : b.plans)
+    if (q.nb == 0) {
+      pl = &q;
+      break;
+    }
+  if (!pl) {
+    pl = &b.plans[1];  // replace the remainder plan
+    if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
+    dfree(p, pl->d_order, sizeof(int32_t) * pl->n_order);
+    dfree(p, pl->d_row_items, sizeof(int2) * pl->n_row);
+    dfree(p, pl->d_tile_items, sizeof(int2) * pl->n_tile);
+    dfree(p, pl->d_val_items, sizeof(int2) * pl->n_val);
+    *pl = pcv_batch_plan{};
+  }
+  const int S = p->S;
+  std::vector<int32_t> order;
+  std::vector<int2> rows, vals;
+  for (int32_t i : p->order_eval)
+    for (int t = 0; t < nb; ++t) {
+      const int32_t k = t * S + i;
+      order.push_back(k);
+      for (int rb = 0; rb < p->desc[i].npad / TB; ++rb) rows.push_back(make_int2(k, rb));
+      for (int vb = 0; vb < (p->desc[i].m + 63) / 64; ++vb) vals.push_back(make_int2(k, vb));
+    }
+  std::vector<int2> tiles = rows;
+  std::stable_sort(tiles.begin(), tiles.end(), [](const int2& a, const int2& c) { return a.y > c.y; });
+  pcv_status s;
+  if ((s = upload(p, &pl->d_order, order)) != PCV_OK) return s;
+  if ((s = upload(p, &pl->d_row_items, rows)) != PCV_OK) return s;
+  if ((s = upload(p, &pl->d_tile_items, tiles)) != PCV_OK) return s;
+  if ((s = upload(p, &pl->d_val_items, vals)) != PCV_OK) return s;
+  pl->n_order = (int)order.size();
+  pl->n_row = (int)rows.size();
+  pl->n_tile = (int)tiles.size();
+  pl->n_val = (int)vals.size();
+  pl->nb = nb;
+  *out = pl;
+  return PCV_OK;
+}
+
+// One launch per kernel over the plan's (slot, subset) pairs, as in a
+// single evaluation (upload of the theta slots, factorisation, solves,
+// refinement, kriging of the validation points, per-slot reductions,
+// download of the per-slot losses and fallback counts).
+pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t st, bool mixed, int sweeps,
+                         bool ev) {
+  pcv_batch& b = p->batch;
+  Launch Lc{st, b.d_desc, b.d_theta};
+  const int nb = pl.nb;
+  HIPCHK(hipMemcpyAsync(b.d_theta, b.h_theta, sizeof(ThetaDev) * nb, hipMemcpyHostToDevice, st));
+  if (ev) HIPCHK(hipEventRecord(p->ev[0], st));
+  if (mixed) {
+    float* L = (float*)b.d_L;
+    HIPCHK(launch_potrf_f32(Lc, pl.d_order, pl.n_order, p->d_px32, p->d_py32, L, b.d_Inv, b.d_logdet, b.d_status));
+    if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
+    HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));
+    HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_alpha, nullptr));
+    if (ev) HIPCHK(hipEventRecord(p->ev[2], st));
+    for (int it = 0; it < sweeps; ++it) {
+      HIPCHK(launch_residual(Lc, pl.d_tile_items, pl.n_tile, pl.d_row_items, pl.n_row, p->d_tx, p->d_ty, p->d_yT,
+                             b.d_alpha, b.d_rrow, b.d_pcol, b.d_r));
+      HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, nullptr, b.d_r, b.d_z,
+                                 b.d_rhs2));
+      HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_x, b.d_alpha));
+    }
+  } else {
+    double* L = (double*)b.d_L;
+    HIPCHK(launch_potrf_f64(Lc, pl.d_order, pl.n_order, p->d_px64, p->d_py64, L, b.d_Inv, b.d_logdet, b.d_status));
+    if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
+    HIPCHK(launch_trsv_fwd_f64(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));
+    HIPCHK(launch_trsv_bwd_f64(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_alpha, nullptr));
+    if (ev) HIPCHK(hipEventRecord(p->ev[2], st));
+  }
+  if (ev) HIPCHK(hipEventRecord(p->ev[3], st));
+  HIPCHK(launch_predict_val(Lc, pl.d_val_items, pl.n_val, p->d_tx, p->d_ty, p->d_vx, p->d_vy, p->d_yV, b.d_alpha,
+                            b.d_yhat, b.d_err));
+  if (ev) HIPCHK(hipEventRecord(p->ev[4], st));
+  HIPCHK(launch_reduce(st, b.d_desc, p->S, nb, b.d_err, b.d_status, p->d_active, sweeps > 0 ? b.d_rhs2 : nullptr,
+                       p->d_ynorm2, p->opt.refine_tol, b.d_sspe, b.d_total, b.d_nbad));
+  if (ev) HIPCHK(hipEventRecord(p->ev[5], st));
+  HIPCHK(hipMemcpyAsync(b.h_total, b.d_total, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(b.h_nbad, b.d_nbad, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+  return PCV_OK;
+}
+
+}  // namespace
+
+pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, double* losses,
+                           pcv_eval_report* rep) {
+  const double t0 = now_s();
+  HIPCHK(hipSetDevice(p->device));
+  if (rep) {
+    rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
+    rep->n_fallback_fp64 = 0;
+    rep->n_val = p->n_val_total;
+    rep->n_subsets_used = p->n_active;
+  }
+  const bool mixed = p->opt.prec == PCV_PREC_MIXED;
+  const int sweeps = mixed ? p->opt.max_refine : 0;
+  // theta slots that fit the batch budget (the cap, else 16 GiB), at most 64
+  const size_t slot = batch_slot_bytes(p, mixed);
+  size_t budget = (size_t)16 << 30;
+  if (p->opt.mem_cap_bytes) budget = p->opt.mem_cap_bytes > p->dev_bytes ? p->opt.mem_cap_bytes - p->dev_bytes : 0;
+  int B = (int)std::min<size_t>({(size_t)64, (size_t)K, budget / std::max<size_t>(slot, 1)});
+  if (p->batch.B > 0) B = std::min(std::max(B, 1), p->batch.B);
+  if (K < 2 || B < 2 || p->n_active == 0) {
+    for (int32_t k = 0; k < K; ++k) {
+      pcv_eval_report r1;
+      std::memset(&r1, 0, sizeof(r1));
+      pcv_status s = eval_impl(p, thetas[k], &losses[k], rep ? &r1 : nullptr);
+      if (s != PCV_OK) return s;
+      if (rep) {
+        rep->ms_factor += r1.ms_factor;
+        rep->ms_solve += r1.ms_solve;
+        rep->ms_refine += r1.ms_refine;
+        rep->ms_predict += r1.ms_predict;
+        rep->ms_reduce += r1.ms_reduce;
+        rep->n_fallback_fp64 += r1.n_fallback_fp64;
+      }
+    }
+    if (rep) rep->seconds = now_s() - t0;
+    return PCV_OK;
+  }
+  pcv_status s = ensure_batch(p, B, mixed);
+  if (s != PCV_OK) return s;
+  pcv_batch& b = p->batch;
+  for (int32_t g0 = 0; g0 < K; g0 += B) {
+    const int nb = std::min(B, K - g0);
+    for (int t = 0; t < nb; ++t) {
+      const pcv_theta& th = thetas[g0 + t];
+      ThetaDev& h = b.h_theta[t];
+      h.cov = th.cov;
+      h.pad = 0;
+      h.range = th.range;
+      h.inv_range = 1.0 / th.range;
+      h.lambda = th.lambda;
+      h.sigma2 = th.sigma2;
+    }
+    pcv_batch_plan* pl = nullptr;
+    if ((s = batch_plan(p, nb, &pl)) != PCV_OK) return s;
+    const bool ev = p->events && rep;
+    if (p->opt.graph && !ev) {
+      if (!pl->graph) {
+        hipStream_t cs = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          s = enqueue_batch(p, *pl, cs, mixed, sweeps, false);
+          e = hipStreamEndCapture(cs, &g);
+        }
+        if (s == PCV_OK && e == hipSuccess) e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        if (s != PCV_OK) return s;
+        if (e != hipSuccess) {
+          pl->graph = nullptr;
+          return fail(PCV_ERR_DEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+        }
+      }
+      HIPCHK(hipGraphLaunch(pl->graph, p->stream));
+    } else {
+      if ((s = enqueue_batch(p, *pl, p->stream, mixed, sweeps, ev)) != PCV_OK) return s;
+    }
+    HIPCHK(hipStreamSynchronize(p->stream));
+    if (ev) {
+      float ms[5];
+      for (int k = 0; k < 5; ++k) HIPCHK(hipEventElapsedTime(&ms[k], p->ev[k], p->ev[k + 1]));
+      rep->ms_factor += ms[0];
+      rep->ms_solve += ms[1];
+      rep->ms_refine += ms[2];
+      rep->ms_predict += ms[3];
+      rep->ms_reduce += ms[4];
+    }
+    for (int t = 0; t < nb; ++t) {
+      if (b.h_nbad[t] > 0 || (mixed && (p->opt.debug_flags & 1))) {
+        // a subset broke down or did not converge: this theta goes through
+        // the single evaluation, which re-runs those subsets in FP64
+        s = eval_impl(p, thetas[g0 + t], &losses[g0 + t], nullptr);
+        if (s != PCV_OK) return s;
+        if (rep) ++rep->n_fallback_fp64;
+      } else {
+        losses[g0 + t] = b.h_total[t];
+      }
+    }
+  }
+  if (rep) rep->seconds = now_s() - t0;
   return PCV_OK;
 }
 

@@ -91,6 +91,8 @@ def lib():
                                      _c_double_p, ctypes.POINTER(Options)]
     L.pcv_eval.argtypes = [P, ctypes.POINTER(Theta), _c_double_p, ctypes.POINTER(EvalReport)]
     L.pcv_eval_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p]
+    L.pcv_eval_batch_ex.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p,
+                                    ctypes.POINTER(EvalReport)]
     L.pcv_factor.argtypes = [P, ctypes.POINTER(Theta)]
     L.pcv_factor_local.argtypes = [P, ctypes.POINTER(Theta)]
     L.pcv_gls.argtypes = [P, ctypes.c_int32, _c_double_p, _c_double_p, _c_int32_p]
@@ -115,7 +117,7 @@ def lib():
     L.pcv_last_error.restype = ctypes.c_char_p
     for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
               "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create", "pcv_factor_local",
-              "pcv_eval_grid", "pcv_gls",
+              "pcv_eval_grid", "pcv_gls", "pcv_eval_batch_ex",
               "pcv_server_submit_predict", "pcv_server_submit_eval", "pcv_server_wait",
               "pcv_server_stats", "pcv_server_report_get", "pcv_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
@@ -219,12 +221,22 @@ class Problem:
                  per_subset_neg2loglik=nll)
         return loss.value, d
 
-    def eval_batch(self, thetas):
+    def eval_batch(self, thetas, report=False):
+        """Losses of several theta values, evaluated together; with
+        report=True also the batch report (wall time, summed phase times when
+        profiling, theta values evaluated again on their own)."""
         L = lib()
         arr = (Theta * len(thetas))(*thetas)
         out = np.zeros(len(thetas))
-        _check(L.pcv_eval_batch(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double)))
-        return out
+        if not report:
+            _check(L.pcv_eval_batch(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double)))
+            return out
+        rep = EvalReport()
+        _check(L.pcv_eval_batch_ex(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double),
+                                   ctypes.byref(rep)))
+        d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
+             if not k.startswith("per_subset") and k != "pad0"}
+        return out, d
 
     def eval_grid(self, thetas):
         """Losses, per-subset losses [K][S] and the best local theta index of

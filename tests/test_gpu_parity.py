@@ -238,13 +238,31 @@ def test_repeatable_bitwise(w_batched_small):
     assert a == b
 
 
-def test_eval_batch_matches_single(w_plain):
-    g = W.theta_grid(w_plain.theta_true, 3)
-    ths = [pcv.theta(*t) for t in g]
-    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+@pytest.mark.parametrize("prec,graph", [("mixed", True), ("mixed", False), ("fp64", True)])
+def test_eval_batch_matches_single(w_batched_small, prec, graph):
+    """Several theta in one launch per kernel (descriptors replicated per
+    theta slot): every loss equals the single evaluation bit for bit.  70
+    values = a group of 64 slots and a remainder group of 6."""
+    r = _rng(30)
+    t0, l0 = w_batched_small.theta_true
+    ths = [pcv.theta(t0 * 2 ** r.uniform(-1, 1), l0 * 2 ** r.uniform(-1, 1)) for _ in range(70)]
+    say(f"[case] eval_batch prec={prec} graph={graph} K=70")
+    with pcv.Problem.from_workload(w_batched_small, prec=prec, graph=graph) as P:
         batch = P.eval_batch(ths)
         single = [P.eval(t) for t in ths]
+        again = P.eval_batch(ths[:9])
     np.testing.assert_array_equal(batch, single)
+    np.testing.assert_array_equal(again, single[:9])
+
+
+def test_eval_batch_with_forced_fallback(w_plain):
+    ths = [pcv.theta(*t) for t in W.theta_grid(w_plain.theta_true, 2)]
+    say("[case] eval_batch forced fallback")
+    with pcv.Problem.from_workload(w_plain, prec="mixed", debug_flags=1) as P:
+        batch = P.eval_batch(ths)
+    with pcv.Problem.from_workload(w_plain, prec="fp64") as P:
+        ref = [P.eval(t) for t in ths]
+    np.testing.assert_array_equal(batch, ref)
 
 
 # ------------------------------------------------------------ prediction --
