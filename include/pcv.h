@@ -224,6 +224,43 @@ pcv_status pcv_problem_info(const pcv_problem* p, int32_t* S, int64_t* nnz_train
 const char* pcv_status_string(pcv_status s);
 const char* pcv_last_error(void);
 
+/* -------------------------------------------------------- partitioning --
+ * The division of Sec. 2.3 / 2.4 (Algorithm 1, steps 2-3) on the device: the
+ * input preparation for pcv_problem_create.  Rectangles are (xlo, ylo, xhi,
+ * yhi), half-open [lo, hi) per axis with edges on the domain maximum closed
+ * (the domain is the bounding box of the cores).  A core's shell is its
+ * rectangle widened by delta on every side, clipped to the domain, minus the
+ * core; shells add training points only.  Temporary device memory is
+ * allocated and freed inside each call.  Results are deterministic. */
+
+/* Recursive balanced division of `domain` (float64 [4]) into m cores
+ * (Sec. 2.4): the x-range is split first and the axes alternate; a
+ * rectangle with k cores is cut into floor(k/2) : ceil(k/2) cores where the
+ * point counts of the two halves, each with its shell of width delta, are in
+ * that ratio (64 bisection steps on the cut; without shells the cut is moved
+ * midway between the neighbouring coordinates).  core_rect: host float64
+ * [m][4] out, in depth-first order (lower / left half first). */
+pcv_status pcv_part_divide(int64_t n, const double* locs, const double* domain, int32_t m, double delta,
+                           double* core_rect);
+
+/* Total memberships sum_i |core_i + shell_i| of all n points for the cores
+ * and delta (the quantity the overlap of a division is set by). */
+pcv_status pcv_part_count(int64_t n, const double* locs, int32_t S, const double* core_rect, double delta,
+                          int64_t* memberships);
+
+/* Subsets of the cores: owner (host int32 [n] out, may be NULL) is the core
+ * of every point (lowest index on shared edges); subset i trains on the
+ * points of core i and of its shell that are not held out (is_val: host
+ * uint8 [n], nonzero = held out, may be NULL = none) and validates on the
+ * held-out points of core i.  train_ptr / val_ptr: host int64 [S+1] out
+ * (may be NULL); train_idx / val_idx: host int32 out of train_ptr[S] /
+ * val_ptr[S] entries, increasing within each subset (may be NULL: call once
+ * for the sizes, then again for the lists).
+ * Errors: PCV_ERR_INVALID (arguments; a point outside every core). */
+pcv_status pcv_part_subsets(int64_t n, const double* locs, int32_t S, const double* core_rect, double delta,
+                            const uint8_t* is_val, int32_t* owner, int64_t* train_ptr, int32_t* train_idx,
+                            int64_t* val_ptr, int32_t* val_idx);
+
 /* ------------------------------------------------------------ serving --
  * A server owns a resident problem while it exists (do not call the
  * pcv_problem functions on it meanwhile) and accepts, from any number of

@@ -256,6 +256,61 @@ pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* m
   return pcv::predict_impl(p, q, qlocs, mean, var, obs_noise, owner);
 }
 
+namespace {
+pcv_status check_points(int64_t n, const double* locs) {
+  if (n < 1 || !locs) return fail(PCV_ERR_INVALID, "n must be >= 1 and locs non-NULL");
+  if (n > INT32_MAX) return fail(PCV_ERR_INVALID, "at most 2^31 - 1 points");
+  for (int64_t j = 0; j < 2 * n; ++j)
+    if (!is_finite(locs[j])) return fail(PCV_ERR_INVALID, "non-finite location");
+  return PCV_OK;
+}
+pcv_status check_rects(int32_t S, const double* R) {
+  if (S < 1 || !R) return fail(PCV_ERR_INVALID, "S must be >= 1 and core_rect non-NULL");
+  for (int64_t j = 0; j < 4 * (int64_t)S; ++j)
+    if (!is_finite(R[j])) return fail(PCV_ERR_INVALID, "non-finite core rectangle");
+  for (int32_t i = 0; i < S; ++i)
+    if (!(R[4 * i] <= R[4 * i + 2]) || !(R[4 * i + 1] <= R[4 * i + 3]))
+      return fail(PCV_ERR_INVALID, "core rectangle " + std::to_string(i) + " has lo > hi");
+  return PCV_OK;
+}
+}  // namespace
+
+pcv_status pcv_part_divide(int64_t n, const double* locs, const double* domain, int32_t m, double delta,
+                           double* core_rect) {
+  pcv::g_err.clear();
+  pcv_status s = check_points(n, locs);
+  if (s != PCV_OK) return s;
+  if (!domain || !core_rect || m < 1) return fail(PCV_ERR_INVALID, "bad domain, m or output");
+  if (!is_finite(delta) || delta < 0) return fail(PCV_ERR_INVALID, "delta must be finite and >= 0");
+  if (!(domain[0] <= domain[2]) || !(domain[1] <= domain[3])) return fail(PCV_ERR_INVALID, "domain has lo > hi");
+  return pcv::part_divide(n, locs, domain, m, delta, core_rect);
+}
+
+pcv_status pcv_part_count(int64_t n, const double* locs, int32_t S, const double* core_rect, double delta,
+                          int64_t* memberships) {
+  pcv::g_err.clear();
+  pcv_status s = check_points(n, locs);
+  if (s == PCV_OK) s = check_rects(S, core_rect);
+  if (s != PCV_OK) return s;
+  if (!memberships) return fail(PCV_ERR_INVALID, "memberships is NULL");
+  if (!is_finite(delta) || delta < 0) return fail(PCV_ERR_INVALID, "delta must be finite and >= 0");
+  return pcv::part_subsets(n, locs, S, core_rect, delta, nullptr, nullptr, memberships, nullptr, nullptr,
+                           nullptr, nullptr);
+}
+
+pcv_status pcv_part_subsets(int64_t n, const double* locs, int32_t S, const double* core_rect, double delta,
+                            const uint8_t* is_val, int32_t* owner, int64_t* train_ptr, int32_t* train_idx,
+                            int64_t* val_ptr, int32_t* val_idx) {
+  pcv::g_err.clear();
+  pcv_status s = check_points(n, locs);
+  if (s == PCV_OK) s = check_rects(S, core_rect);
+  if (s != PCV_OK) return s;
+  if (!is_finite(delta) || delta < 0) return fail(PCV_ERR_INVALID, "delta must be finite and >= 0");
+  if ((train_idx && !train_ptr) || (val_idx && !val_ptr)) return fail(PCV_ERR_INVALID, "index list without ptr");
+  return pcv::part_subsets(n, locs, S, core_rect, delta, is_val, owner, nullptr, train_ptr, train_idx, val_ptr,
+                           val_idx);
+}
+
 pcv_status pcv_server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight) {
   pcv::g_err.clear();
   if (!out) return fail(PCV_ERR_INVALID, "out is NULL");

@@ -150,6 +150,12 @@ pcv_status server_report(pcv_server* s, pcv_server_report* out);
 pcv_status server_destroy(pcv_server* s);
 const pcv_problem* server_problem(const pcv_server* s);
 
+pcv_status part_divide(int64_t n, const double* locs, const double* domain, int32_t m, double delta,
+                       double* core_rect);
+pcv_status part_subsets(int64_t n, const double* locs, int32_t S, const double* core_rect, double delta,
+                        const uint8_t* is_val, int32_t* owner, int64_t* memberships, int64_t* train_ptr,
+                        int32_t* train_idx, int64_t* val_ptr, int32_t* val_idx);
+
 // Owning subset of each query location (half-open cores, nearest core
 // outside all of them; nearest training centroid without core rectangles).
 void route(const pcv_problem* p, int64_t q, const double* ql, int32_t* owner);

@@ -298,23 +298,43 @@ void completer(pcv_server* s) {
   }
 }
 
+// Evaluations queued together run as one batch (several theta values per
+// launch when the workspace allows; results identical to one at a time).
 void evaluator(pcv_server* s) {
   (void)hipSetDevice(s->p->device);
+  std::vector<Req*> batch;
+  std::vector<pcv_theta> th;
+  std::vector<double> loss;
   for (;;) {
-    Req* r;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_eval.wait(lk, [&] { return s->stop || !s->eval_q.empty(); });
       if (s->eval_q.empty()) break;  // stop requested and nothing left
-      r = s->eval_q.front();
-      s->eval_q.pop_front();
+      batch.clear();
+      while (!s->eval_q.empty() && batch.size() < 64) {
+        batch.push_back(s->eval_q.front());
+        s->eval_q.pop_front();
+      }
     }
-    double loss = 0.0;
+    th.resize(batch.size());
+    loss.assign(batch.size(), 0.0);
+    for (size_t k = 0; k < batch.size(); ++k) th[k] = batch[k]->th;
     g_err.clear();
-    const pcv_status st = eval_impl(s->p, r->th, &loss, nullptr);
-    if (st == PCV_OK) *r->loss = loss;
+    pcv_status st = eval_batch_impl(s->p, (int32_t)batch.size(), th.data(), loss.data(), nullptr);
+    std::vector<pcv_status> sts(batch.size(), st);
+    std::vector<std::string> errs(batch.size(), st == PCV_OK ? "" : g_err);
+    if (st != PCV_OK && batch.size() > 1) {
+      // find which ones fail: evaluate them one by one
+      for (size_t k = 0; k < batch.size(); ++k) {
+        g_err.clear();
+        sts[k] = eval_impl(s->p, th[k], &loss[k], nullptr);
+        errs[k] = sts[k] == PCV_OK ? "" : g_err;
+      }
+    }
+    for (size_t k = 0; k < batch.size(); ++k)
+      if (sts[k] == PCV_OK) *batch[k]->loss = loss[k];
     std::lock_guard<std::mutex> lk(s->mu);
-    finish_locked(s, r, st, st == PCV_OK ? "" : g_err);
+    for (size_t k = 0; k < batch.size(); ++k) finish_locked(s, batch[k], sts[k], errs[k]);
   }
 }
 

@@ -20,6 +20,11 @@ Conventions (readings where the paper is silent):
     halves proportional to those core counts (Sec. 2.4 balances them).
   * Optional size cap: subsets above `cap` training points are subsampled,
     shell points dropped first (Sec. 4.3.2 caps shells by random sampling).
+
+recursive_cores, count_memberships and build_partition take device=True to
+run the geometry on the GPU (the library's pcv_part_* calls), with results
+identical to the host code; the random hold-out split and the cap are drawn
+on the host in both cases.
 """
 from dataclasses import dataclass, field
 
@@ -102,7 +107,7 @@ def grid_cores(domain, nx, ny):
     return np.array(rects, dtype=np.float64)
 
 
-def recursive_cores(P, domain, m, delta):
+def recursive_cores(P, domain, m, delta, device=False):
     """Recursive balanced division of Sec. 2.4 into m cores.
 
     Splits alternate between the x-range (first) and the y-range.  Each split
@@ -111,6 +116,9 @@ def recursive_cores(P, domain, m, delta):
     receives.  Cores are returned in depth-first (left/bottom first) order.
     """
     P = np.asarray(P, dtype=np.float64)
+    if device:
+        from . import pcv
+        return pcv.part_divide(P, domain, m, delta)
     out = []
     stack = [(np.array(domain, dtype=np.float64), m, 0, np.arange(P.shape[0]))]
     while stack:
@@ -199,18 +207,21 @@ def _shell_members(P, core_rect, delta, eligible, bk):
     return out
 
 
-def count_memberships(P, core_rect, delta):
+def count_memberships(P, core_rect, delta, device=False):
     """Total number of (point, subset) memberships: sum over subsets of the
     points in core + shell (all points, before any split)."""
     P = np.asarray(P, dtype=np.float64)
     R = np.asarray(core_rect, dtype=np.float64)
+    if device:
+        from . import pcv
+        return pcv.part_count(P, R, delta)
     domain = (R[:, 0].min(), R[:, 1].min(), R[:, 2].max(), R[:, 3].max())
     bk = _Buckets(P, domain)
     shells = _shell_members(P, R, delta, np.ones(P.shape[0], dtype=bool), bk)
     return P.shape[0] + sum(s.shape[0] for s in shells)
 
 
-def find_delta(P, core_fn, overlap, tol=0.005, iters=40):
+def find_delta(P, core_fn, overlap, tol=0.005, iters=40, device=False):
     """Shell width delta such that the total memberships equal
     (1 + overlap) * N within tol (relative).  core_fn(delta) -> core
     rectangles (the recursive division depends on delta; a grid does not).
@@ -227,7 +238,7 @@ def find_delta(P, core_fn, overlap, tol=0.005, iters=40):
 
     def g(d):
         R = core_fn(d)
-        c = count_memberships(P, R, d)
+        c = count_memberships(P, R, d, device=device)
         return c - target, R, c
 
     lo, glo, best = 0.0, N - target, (0.0, R0, N)
@@ -262,7 +273,7 @@ def find_delta(P, core_fn, overlap, tol=0.005, iters=40):
     return best
 
 
-def build_partition(P, core_rect, delta, val_frac, rng, cap=None):
+def build_partition(P, core_rect, delta, val_frac, rng, cap=None, device=False):
     """CSR subsets from cores: validation split per core, then each subset's
     training set = training points of its core plus its shell (Sec. 2.3).
 
@@ -270,6 +281,8 @@ def build_partition(P, core_rect, delta, val_frac, rng, cap=None):
     P = np.asarray(P, dtype=np.float64)
     R = np.asarray(core_rect, dtype=np.float64)
     S = R.shape[0]
+    if device:
+        return _build_partition_device(P, R, delta, val_frac, rng, cap)
     owner = assign_cores(P, R)
     order = np.argsort(owner, kind="stable")
     starts = np.searchsorted(owner[order], np.arange(S + 1))
@@ -306,6 +319,50 @@ def build_partition(P, core_rect, delta, val_frac, rng, cap=None):
     vptr[1:] = np.cumsum([v.shape[0] for v in val_lists])
     tidx = np.concatenate(train_lists).astype(np.int32) if S else np.zeros(0, np.int32)
     vidx = np.concatenate(val_lists).astype(np.int32) if S else np.zeros(0, np.int32)
+    info = dict(memberships=int(tptr[-1] + vptr[-1]), n_capped=n_capped,
+                train_min=int(np.diff(tptr).min()), train_max=int(np.diff(tptr).max()),
+                val_total=int(vptr[-1]))
+    return Partition(core_rect=R, delta=float(delta), train_ptr=tptr, train_idx=tidx,
+                     val_ptr=vptr, val_idx=vidx, owner=owner, is_val=is_val, info=info)
+
+
+def _split(owner, S, val_frac, rng):
+    """The per-core hold-out draw (the same calls in the same order as the
+    host path of build_partition)."""
+    order = np.argsort(owner, kind="stable")
+    starts = np.searchsorted(owner[order], np.arange(S + 1))
+    is_val = np.zeros(owner.shape[0], dtype=bool)
+    for i in range(S):
+        members = order[starts[i]:starts[i + 1]]
+        nv = int(round(val_frac * members.shape[0]))
+        pick = rng.choice(members.shape[0], size=nv, replace=False) if nv else np.zeros(0, np.int64)
+        is_val[members[pick]] = True
+    return is_val
+
+
+def _build_partition_device(P, R, delta, val_frac, rng, cap):
+    from . import pcv
+    S = R.shape[0]
+    owner = pcv.part_subsets(P, R, delta, lists=False)
+    is_val = _split(owner, S, val_frac, rng)
+    _, tptr, tidx, vptr, vidx = pcv.part_subsets(P, R, delta, is_val=is_val)
+    n_capped = 0
+    if cap is not None:
+        # the host path's cap, in the same order: shell points dropped first
+        lists = []
+        for i in range(S):
+            t = tidx[tptr[i]:tptr[i + 1]]
+            ct, sh = t[owner[t] == i], t[owner[t] != i]
+            if ct.shape[0] + sh.shape[0] > cap:
+                n_capped += 1
+                keep_shell = max(cap - ct.shape[0], 0)
+                sh = sh[np.sort(rng.choice(sh.shape[0], size=keep_shell, replace=False))] if keep_shell else sh[:0]
+                if ct.shape[0] > cap:
+                    ct = ct[np.sort(rng.choice(ct.shape[0], size=cap, replace=False))]
+            lists.append(np.sort(np.concatenate([ct, sh])))
+        tptr = np.zeros(S + 1, dtype=np.int64)
+        tptr[1:] = np.cumsum([t.shape[0] for t in lists])
+        tidx = np.concatenate(lists).astype(np.int32) if S else np.zeros(0, np.int32)
     info = dict(memberships=int(tptr[-1] + vptr[-1]), n_capped=n_capped,
                 train_min=int(np.diff(tptr).min()), train_max=int(np.diff(tptr).max()),
                 val_total=int(vptr[-1]))

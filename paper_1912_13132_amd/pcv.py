@@ -111,13 +111,21 @@ def lib():
     L.pcv_server_stats.argtypes = [P, _c_double_p, _c_double_p, _c_double_p, _c_double_p]
     L.pcv_server_report_get.argtypes = [P, ctypes.POINTER(ServerReport)]
     L.pcv_server_destroy.argtypes = [P]
+    L.pcv_part_divide.argtypes = [ctypes.c_int64, _c_double_p, _c_double_p, ctypes.c_int32, ctypes.c_double,
+                                  _c_double_p]
+    L.pcv_part_count.argtypes = [ctypes.c_int64, _c_double_p, ctypes.c_int32, _c_double_p, ctypes.c_double,
+                                 _c_int64_p]
+    L.pcv_part_subsets.argtypes = [ctypes.c_int64, _c_double_p, ctypes.c_int32, _c_double_p, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_uint8), _c_int32_p, _c_int64_p, _c_int32_p,
+                                   _c_int64_p, _c_int32_p]
     L.pcv_status_string.argtypes = [ctypes.c_int]
     L.pcv_status_string.restype = ctypes.c_char_p
     L.pcv_last_error.argtypes = []
     L.pcv_last_error.restype = ctypes.c_char_p
     for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
               "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create", "pcv_factor_local",
-              "pcv_eval_grid", "pcv_gls", "pcv_eval_batch_ex",
+              "pcv_eval_grid", "pcv_gls", "pcv_eval_batch_ex", "pcv_part_divide", "pcv_part_count",
+              "pcv_part_subsets",
               "pcv_server_submit_predict", "pcv_server_submit_eval", "pcv_server_wait",
               "pcv_server_stats", "pcv_server_report_get", "pcv_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
@@ -148,6 +156,51 @@ def _stream_handle(stream):
     if hasattr(stream, "cuda_stream"):      # torch.cuda.Stream
         return int(stream.cuda_stream)
     return int(stream)
+
+
+def part_divide(locs, domain, m, delta):
+    """Recursive balanced division into m cores on the device (Sec. 2.4)."""
+    P = _as(locs, np.float64).reshape(-1, 2)
+    dom = _as(domain, np.float64)
+    out = np.zeros((int(m), 4))
+    _check(lib().pcv_part_divide(P.shape[0], _ptr(P, ctypes.c_double), _ptr(dom, ctypes.c_double), int(m),
+                                 float(delta), _ptr(out, ctypes.c_double)))
+    return out
+
+
+def part_count(locs, core_rect, delta):
+    """Total core + shell memberships of all points on the device."""
+    P = _as(locs, np.float64).reshape(-1, 2)
+    R = _as(core_rect, np.float64).reshape(-1, 4)
+    c = ctypes.c_int64()
+    _check(lib().pcv_part_count(P.shape[0], _ptr(P, ctypes.c_double), R.shape[0], _ptr(R, ctypes.c_double),
+                                float(delta), ctypes.byref(c)))
+    return c.value
+
+
+def part_subsets(locs, core_rect, delta, is_val=None, lists=True):
+    """Owner of every point and, with lists=True, the training / validation
+    CSR of the subsets (device construction)."""
+    P = _as(locs, np.float64).reshape(-1, 2)
+    R = _as(core_rect, np.float64).reshape(-1, 4)
+    n, S = P.shape[0], R.shape[0]
+    owner = np.zeros(n, dtype=np.int32)
+    tp = np.zeros(S + 1, dtype=np.int64)
+    vp = np.zeros(S + 1, dtype=np.int64)
+    iv = None if is_val is None else _as(is_val, np.uint8)
+    ivp = None if iv is None else iv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    L = lib()
+    args = (n, _ptr(P, ctypes.c_double), S, _ptr(R, ctypes.c_double), float(delta), ivp)
+    if not lists:
+        _check(L.pcv_part_subsets(*args, _ptr(owner, ctypes.c_int32), None, None, None, None))
+        return owner
+    _check(L.pcv_part_subsets(*args, _ptr(owner, ctypes.c_int32), _ptr(tp, ctypes.c_int64), None,
+                              _ptr(vp, ctypes.c_int64), None))
+    ti = np.zeros(int(tp[-1]), dtype=np.int32)
+    vi = np.zeros(int(vp[-1]), dtype=np.int32)
+    _check(L.pcv_part_subsets(*args, None, _ptr(tp, ctypes.c_int64), _ptr(ti, ctypes.c_int32),
+                              _ptr(vp, ctypes.c_int64), _ptr(vi, ctypes.c_int32)))
+    return owner, tp, ti, vp, vi
 
 
 class Problem:

@@ -91,7 +91,7 @@ def _bilinear(F, x0, y0, hx, hy, P):
 
 
 # ------------------------------------------------------------- workloads ---
-def plain_fp64(n=2000, grid=(2, 2), overlap=0.1, val_frac=0.1, seed_id=1):
+def plain_fp64(n=2000, grid=(2, 2), overlap=0.1, val_frac=0.1, seed_id=1, device=False):
     r_loc, r_field, r_split, _, _ = streams(seed_id)
     P = r_loc.uniform(0.0, 1.0, size=(n, 2))
     dx = P[:, 0][:, None] - P[:, 0][None, :]
@@ -100,13 +100,13 @@ def plain_fp64(n=2000, grid=(2, 2), overlap=0.1, val_frac=0.1, seed_id=1):
     y = np.linalg.cholesky(C) @ r_field.standard_normal(n)
     dom = (0.0, 0.0, 1.0, 1.0)
     cores = part.grid_cores(dom, *grid)
-    delta, _, cnt = part.find_delta(P, lambda d: cores, overlap)
-    pt = part.build_partition(P, cores, delta, val_frac, r_split)
+    delta, _, cnt = part.find_delta(P, lambda d: cores, overlap, device=device)
+    pt = part.build_partition(P, cores, delta, val_frac, r_split, device=device)
     return Workload("plain_fp64", P, y, pt, COV_EXP, (0.1, 0.05), dom,
                     dict(memberships_all=cnt))
 
 
-def batched(n=100_000, grid=(16, 16), overlap=0.1, val_frac=0.1, lattice=2048, seed_id=2):
+def batched(n=100_000, grid=(16, 16), overlap=0.1, val_frac=0.1, lattice=2048, seed_id=2, device=False):
     r_loc, r_field, r_split, _, _ = streams(seed_id)
     P = r_loc.uniform(0.0, 1.0, size=(n, 2))
     h = 1.0 / (lattice - 1)
@@ -114,8 +114,8 @@ def batched(n=100_000, grid=(16, 16), overlap=0.1, val_frac=0.1, lattice=2048, s
     y = _bilinear(F, 0.0, 0.0, h, h, P) + np.sqrt(0.1) * r_field.standard_normal(n)
     dom = (0.0, 0.0, 1.0, 1.0)
     cores = part.grid_cores(dom, *grid)
-    delta, _, cnt = part.find_delta(P, lambda d: cores, overlap)
-    pt = part.build_partition(P, cores, delta, val_frac, r_split)
+    delta, _, cnt = part.find_delta(P, lambda d: cores, overlap, device=device)
+    pt = part.build_partition(P, cores, delta, val_frac, r_split, device=device)
     return Workload("batched", P, y, pt, COV_EXP, (0.05, 0.1), dom, dict(memberships_all=cnt))
 
 
@@ -142,7 +142,7 @@ def thomas_points(n, n_parents_mean, sigma, rng):
 
 
 def uneven(n=1_000_000, grid=(32, 32), overlap=0.1, val_frac=0.1, cap=4000,
-           lattice=2048, seed_id=3):
+           lattice=2048, seed_id=3, device=False):
     r_loc, r_field, r_split, _, _ = streams(seed_id)
     P = thomas_points(n, 200, 0.02, r_loc)
     h = 1.0 / (lattice - 1)
@@ -150,8 +150,8 @@ def uneven(n=1_000_000, grid=(32, 32), overlap=0.1, val_frac=0.1, cap=4000,
     y = _bilinear(F, 0.0, 0.0, h, h, P) + np.sqrt(0.02) * r_field.standard_normal(n)
     dom = (0.0, 0.0, 1.0, 1.0)
     cores = part.grid_cores(dom, *grid)
-    delta, _, cnt = part.find_delta(P, lambda d: cores, overlap)
-    pt = part.build_partition(P, cores, delta, val_frac, r_split, cap=cap)
+    delta, _, cnt = part.find_delta(P, lambda d: cores, overlap, device=device)
+    pt = part.build_partition(P, cores, delta, val_frac, r_split, cap=cap, device=device)
     return Workload("uneven", P, y, pt, COV_MATERN32, (0.03, 0.02), dom, dict(memberships_all=cnt))
 
 
@@ -187,7 +187,7 @@ LARGE_DELTA = None   # shell width found by find_delta on the large workload
 
 
 def large(n=5_000_000, nx=2170, ny=2712, W=2000.0, H=2500.0, n_cores=2400,
-          overlap=0.2, val_frac=0.1, delta=None, seed_id=4):
+          overlap=0.2, val_frac=0.1, delta=None, seed_id=4, device=False):
     r_loc, r_field, r_split, _, _ = streams(seed_id)
     P, (ii, jj), (hx, hy) = jittered_lattice_with_gaps(nx, ny, W, H, 0.15, n, r_loc)
     F = lattice_field(nx, ny, hx, hy, COV_EXP, 50.0, r_field)
@@ -197,11 +197,12 @@ def large(n=5_000_000, nx=2170, ny=2712, W=2000.0, H=2500.0, n_cores=2400,
     info = {}
     if delta is None:
         delta, cores, cnt = part.find_delta(
-            P, lambda d: part.recursive_cores(P, dom, n_cores, d), overlap, iters=20)
+            P, lambda d: part.recursive_cores(P, dom, n_cores, d, device=device), overlap, iters=20,
+            device=device)
         info["memberships_all"] = cnt
     else:
-        cores = part.recursive_cores(P, dom, n_cores, delta)
-    pt = part.build_partition(P, cores, delta, val_frac, r_split)
+        cores = part.recursive_cores(P, dom, n_cores, delta, device=device)
+    pt = part.build_partition(P, cores, delta, val_frac, r_split, device=device)
     return Workload("large", P, y, pt, COV_EXP, (50.0, 0.1), dom, info)
 
 

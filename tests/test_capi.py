@@ -108,3 +108,17 @@ def test_server_calls_reject_null_handles():
     assert L.pcv_server_report_get(None, None) == 1
     assert L.pcv_server_destroy(None) == 1
     assert b"NULL" in L.pcv_last_error()
+
+
+def test_partition_calls_validate_before_device_work():
+    P = np.array([[0.1, 0.2], [0.3, np.nan]])
+    dom = np.array([0.0, 0.0, 1.0, 1.0])
+    with pytest.raises(pcv.PcvError) as e:
+        pcv.part_divide(P, dom, 4, 0.0)
+    assert e.value.status == 1
+    with pytest.raises(pcv.PcvError) as e:
+        pcv.part_divide(np.zeros((3, 2)), dom, 4, -1.0)
+    assert e.value.status == 1
+    with pytest.raises(pcv.PcvError) as e:
+        pcv.part_count(np.zeros((3, 2)), np.array([[0.0, 0.0, -1.0, 1.0]]), 0.1)
+    assert e.value.status == 1
