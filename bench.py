@@ -153,7 +153,7 @@ def _oracle_subset(args):
         return time.perf_counter() - t0, r["sspe"]
 
 
-def cpu_baseline(w, th, gpu_per_subset, sample=48, seed=7, workload="large"):
+def cpu_baseline(w, th, gpu_per_subset, sample=144, seed=7, workload="large"):
     import multiprocessing as mp
     pt = w.part
     n = np.diff(pt.train_ptr)
@@ -221,14 +221,14 @@ def main():
     t0 = time.perf_counter()
     if a.workload == "large":
         if a.scale >= 1.0:
-            w = W.large()
+            w = W.large(device=True)
         else:
             s = a.scale
             w = W.large(n=int(5_000_000 * s), nx=int(2170 * math.sqrt(s)) + 1,
                         ny=int(2712 * math.sqrt(s)) + 1, W=2000 * math.sqrt(s), H=2500 * math.sqrt(s),
                         n_cores=max(2, int(2400 * s)))
     else:
-        w = {"plain": W.plain_fp64, "batched": W.batched, "uneven": W.uneven}[a.workload]()
+        w = {"plain": W.plain_fp64, "batched": W.batched, "uneven": W.uneven}[a.workload](device=True)
     pt = w.part
     nT = np.diff(pt.train_ptr)
     mV = np.diff(pt.val_ptr)

@@ -5,7 +5,8 @@
 //
 //  * divide: the recursive balanced division, level by level.  Every
 //    rectangle with k > 1 cores sorts the coordinates of its candidate points
-//    along its split axis (a segmented radix sort), and one wave per
+//    along its split axis (two stable radix sorts over all segments: by
+//    coordinate, then by segment), and one wave per
 //    rectangle repeats the 64 bisection steps on the cut c that balance
 //    k_r #{a < c + delta} against k_l #{a >= c - delta}; counts are found by
 //    a 64-way cooperative search in the sorted segment.  Candidates of the
@@ -345,16 +346,24 @@ pcv_status part_divide(int64_t n, const double* locs, const double* domain, int3
     const unsigned blocks = (unsigned)((total + TPB - 1) / TPB);
     if (total > 0) hipLaunchKernelGGL(k_seg_keys, dim3(blocks), dim3(TPB), 0, 0, drect, nr, cand, total, dx, dy, seg, key);
     PCHK(hipGetLastError());
-    // segmented sort of the keys
-    DevBuf offb;
-    int64_t* doff;
-    PCHK(dmalloc(offb, &doff, nr + 1));
-    PCHK(hipMemcpy(doff, off.data(), 8 * (nr + 1), hipMemcpyHostToDevice));
-    size_t tb = 0;
-    PCHK(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, tb, key, sorted, (int)total, nr, doff, doff + 1));
+    // keys sorted within their segments: a global sort by coordinate, then a
+    // stable global sort by segment (radix sorts are stable)
+    DevBuf k2b, s2b, s3b, tmpb2;
+    double* key2;
+    int32_t *seg2, *seg3;
+    PCHK(dmalloc(k2b, &key2, total));
+    PCHK(dmalloc(s2b, &seg2, total));
+    PCHK(dmalloc(s3b, &seg3, total));
+    size_t tb = 0, tbb = 0;
+    PCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, key2, seg, seg2, (int)total));
+    PCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbb, seg2, seg3, key2, sorted, (int)total));
     char* tmp;
-    PCHK(dmalloc(tmpb, &tmp, tb));
-    PCHK(hipcub::DeviceSegmentedRadixSort::SortKeys((void*)tmp, tb, key, sorted, (int)total, nr, doff, doff + 1));
+    PCHK(dmalloc(tmpb, &tmp, std::max(tb, tbb)));
+    tb = std::max(tb, tbb);
+    if (total > 0) {
+      PCHK(hipcub::DeviceRadixSort::SortPairs((void*)tmp, tb, key, key2, seg, seg2, (int)total));
+      PCHK(hipcub::DeviceRadixSort::SortPairs((void*)tmp, tb, seg2, seg3, key2, sorted, (int)total));
+    }
     hipLaunchKernelGGL(k_bisect, dim3(nr), dim3(64), 0, 0, drect, sorted, delta, cut, dnl, dnr);
     PCHK(hipGetLastError());
     if (total > 0)
