@@ -201,7 +201,7 @@ def main():
                     help="also run a plain device copy of this size (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(subsets would shard across GPUs with one broadcast and one scalar reduce)",
               file=sys.stderr)
         sys.exit(2)

@@ -143,6 +143,23 @@ def test_ragged_sizes_and_degenerate_subsets(prec, tol):
     assert rep["n_val"] == ref["n_val"]
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_subsets_above_4096_points(prec, tol):
+    """Subsets of 5,000 and 4,097 training points take the solve variants
+    for more than 4,096 padded rows; a small subset rides along."""
+    sizes_T = [5000, 4097, 300]
+    sizes_V = [120, 40, 20]
+    locs, y, tp, ti, vp, vi = _synthetic(sizes_T, sizes_V, 5, spread=3.0)
+    say(f"[case] large subsets prec={prec} sizes={sizes_T}")
+    ref = oracle.cv_loss(locs, y, tp, ti, vp, vi, 0, 0.4, 0.1)
+    with pcv.Problem(locs, y, tp, ti, vp, vi, prec=prec) as P:
+        loss, rep = P.eval(pcv.theta(0.4, 0.1), report=True)
+    assert _rel(loss, ref["sspe"]) <= tol
+    np.testing.assert_allclose(rep["per_subset_sspe"], ref["per_subset_sspe"], rtol=100 * tol)
+    np.testing.assert_allclose(rep["per_subset_logdet"], ref["per_subset_logdet"],
+                               rtol=1e-9 if prec == "fp64" else 1e-4)
+
+
 def test_no_nugget_fp64():
     """lambda = 0 is allowed (tau >= 0 in eq. (1)); distinct points keep M SPD."""
     locs, y, tp, ti, vp, vi = _synthetic([120, 90], [10, 10], 2)
