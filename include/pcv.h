@@ -90,7 +90,17 @@ typedef struct {
                              FP64 fallback path runs for every subset              */
   int32_t graph;          /* nonzero (default): capture the theta-evaluation once as a
                              HIP graph and replay it; 0: launch kernel by kernel  */
-  int32_t reserved[5];
+  int32_t inputs_on_device; /* nonzero: every array argument of pcv_problem_create
+                             and pcv_predict (inputs and outputs) is a device
+                             pointer on the current device, e.g. a torch tensor's
+                             data_ptr().  Each must lie inside one device (or
+                             managed) allocation, else PCV_ERR_INVALID.  The
+                             library reads the inputs on hip_stream (with no
+                             hip_stream, after a device-wide synchronisation),
+                             so writes the caller queued there come first;
+                             nothing is kept after the call returns.  The
+                             other calls always take host arrays.  Default 0 */
+  int32_t reserved[4];
 } pcv_options;
 
 /* Per-evaluation report.  Arrays are optional, caller-owned, length S. */
@@ -138,6 +148,7 @@ void pcv_default_options(pcv_options* opt);
  *              route prediction queries; may be NULL (then pcv_predict routes
  *              every query to the subset whose training centroid is nearest)
  *   opt        may be NULL (defaults)
+ * All arrays are device arrays instead when opt->inputs_on_device is set.
  * Subsets without validation points are kept but never evaluated (they
  * contribute 0, as in Sec. 4.3.1).  A subset larger than the library's
  * maximum (PCV_MAX_SUBSET training points) is rejected with PCV_ERR_INVALID.
@@ -198,7 +209,9 @@ pcv_status pcv_factor_local(pcv_problem* p, const pcv_theta* thetas);
  * all), mean = k^T alpha (eq. (3)) and
  * var = sigma^2 (1 - k^T (Sigma + lambda I)^{-1} k) (+ sigma^2 lambda when
  * obs_noise != 0).  var may be NULL.  owner (may be NULL) receives each
- * query's subset.  Errors: PCV_ERR_STATE before pcv_factor. */
+ * query's subset.  With the problem's inputs_on_device option, qlocs, mean,
+ * var and owner are device arrays and the results are in them when the call
+ * returns.  Errors: PCV_ERR_STATE before pcv_factor. */
 pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* mean,
                        double* var, int32_t obs_noise, int32_t* owner);
 

@@ -52,6 +52,61 @@ pcv_status check_theta(const pcv_theta* t) {
   return PCV_OK;
 }
 
+// Device-array arguments (inputs_on_device): each one must lie inside a
+// single device or managed allocation of the current device, checked before
+// any copy so that a wrong pointer or length is an argument error.
+pcv_status check_device_range(const void* ptr, size_t bytes, const char* what) {
+  if (bytes == 0) return PCV_OK;
+  if (!ptr) return fail(PCV_ERR_INVALID, std::string(what) + " is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PCV_ERR_DEVICE, "hipGetDevice failed");
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PCV_ERR_INVALID, std::string(what) + " is not a device pointer (inputs_on_device is set)");
+  }
+  if ((a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) || a.device != dev)
+    return fail(PCV_ERR_INVALID, std::string(what) + " is not memory of the current device");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PCV_ERR_INVALID, std::string(what) + ": no allocation holds it");
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(ptr);
+  if (q < b || (size_t)(q - b) > size || bytes > size - (size_t)(q - b))
+    return fail(PCV_ERR_INVALID, std::string(what) + " extends past the end of its allocation");
+  return PCV_OK;
+}
+
+// Copies device arrays to the host, on the caller's stream when there is one
+// (queued writes come first), else after a device-wide synchronisation.
+struct DeviceReader {
+  hipStream_t s = nullptr;
+  bool ready = false;
+  pcv_status begin(void* stream) {
+    s = (hipStream_t)stream;
+    if (!s && hipDeviceSynchronize() != hipSuccess)
+      return fail(PCV_ERR_DEVICE, "hipDeviceSynchronize failed before reading device inputs");
+    ready = true;
+    return PCV_OK;
+  }
+  template <class T>
+  pcv_status read(std::vector<T>& dst, const T* src, size_t count, const char* what) {
+    pcv_status st = check_device_range(src, count * sizeof(T), what);
+    if (st != PCV_OK) return st;
+    dst.resize(count);
+    if (count == 0) return PCV_OK;
+    hipError_t e = hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+      return fail(PCV_ERR_DEVICE, std::string("reading ") + what + ": " + hipGetErrorString(e));
+    return PCV_OK;
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -92,6 +147,37 @@ pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs, 
   if (!locs || !y) return fail(PCV_ERR_INVALID, "locs and y must be non-NULL");
   if (S < 1) return fail(PCV_ERR_INVALID, "S must be >= 1");
   if (!train_ptr || !val_ptr) return fail(PCV_ERR_INVALID, "train_ptr and val_ptr must be non-NULL");
+  pcv_options o;
+  pcv_default_options(&o);
+  if (opt) o = *opt;
+  // device inputs: host copies, then the same validation as host inputs
+  std::vector<double> h_locs, h_y, h_rect;
+  std::vector<int64_t> h_tp, h_vp;
+  std::vector<int32_t> h_ti, h_vi;
+  if (o.inputs_on_device) {
+    DeviceReader rd;
+    pcv_status st = rd.begin(o.hip_stream);
+    if (st == PCV_OK) st = rd.read(h_tp, train_ptr, (size_t)S + 1, "train_ptr");
+    if (st == PCV_OK) st = rd.read(h_vp, val_ptr, (size_t)S + 1, "val_ptr");
+    if (st != PCV_OK) return st;
+    for (int32_t i = 0; i < S; ++i)
+      if (h_tp[i + 1] < h_tp[i] || h_vp[i + 1] < h_vp[i])
+        return fail(PCV_ERR_INVALID, "ptr array decreases at subset " + std::to_string(i));
+    if (h_tp[0] != 0 || h_vp[0] != 0) return fail(PCV_ERR_INVALID, "ptr arrays must start at 0");
+    if (st == PCV_OK) st = rd.read(h_locs, locs, 2 * (size_t)n, "locs");
+    if (st == PCV_OK) st = rd.read(h_y, y, (size_t)n, "y");
+    if (st == PCV_OK) st = rd.read(h_ti, train_idx, (size_t)h_tp[S], "train_idx");
+    if (st == PCV_OK) st = rd.read(h_vi, val_idx, (size_t)h_vp[S], "val_idx");
+    if (st == PCV_OK && core_rect) st = rd.read(h_rect, core_rect, 4 * (size_t)S, "core_rect");
+    if (st != PCV_OK) return st;
+    locs = h_locs.data();
+    y = h_y.data();
+    train_ptr = h_tp.data();
+    val_ptr = h_vp.data();
+    train_idx = h_ti.empty() ? nullptr : h_ti.data();
+    val_idx = h_vi.empty() ? nullptr : h_vi.data();
+    core_rect = core_rect ? h_rect.data() : nullptr;
+  }
   if (train_ptr[0] != 0 || val_ptr[0] != 0) return fail(PCV_ERR_INVALID, "ptr arrays must start at 0");
   for (int32_t i = 0; i < S; ++i) {
     if (train_ptr[i + 1] < train_ptr[i]) return fail(PCV_ERR_INVALID, "train_ptr decreases at subset " + std::to_string(i));
@@ -111,9 +197,6 @@ pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs, 
   if (core_rect)
     for (int64_t j = 0; j < 4LL * S; ++j)
       if (!is_finite(core_rect[j])) return fail(PCV_ERR_INVALID, "non-finite core_rect");
-  pcv_options o;
-  pcv_default_options(&o);
-  if (opt) o = *opt;
   if (o.prec != PCV_PREC_FP64 && o.prec != PCV_PREC_MIXED) return fail(PCV_ERR_INVALID, "opt.prec invalid");
   if (o.max_refine < 0 || o.max_refine > 8) return fail(PCV_ERR_INVALID, "opt.max_refine must be in [0, 8]");
   if (!(o.refine_tol >= 0.0)) return fail(PCV_ERR_INVALID, "opt.refine_tol must be >= 0");
@@ -250,10 +333,22 @@ pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* m
   pcv::g_err.clear();
   if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
   if (q < 0 || (q > 0 && (!qlocs || !mean))) return fail(PCV_ERR_INVALID, "bad query arguments");
+  std::vector<double> h_q;
+  const bool dev = p->opt.inputs_on_device != 0;
+  if (dev && q > 0) {
+    DeviceReader rd;
+    pcv_status st = check_device_range(mean, sizeof(double) * q, "mean");
+    if (st == PCV_OK && var) st = check_device_range(var, sizeof(double) * q, "var");
+    if (st == PCV_OK && owner) st = check_device_range(owner, sizeof(int32_t) * q, "owner");
+    if (st == PCV_OK) st = rd.begin(p->own_stream ? nullptr : (void*)p->stream);
+    if (st == PCV_OK) st = rd.read(h_q, qlocs, 2 * (size_t)q, "qlocs");
+    if (st != PCV_OK) return st;
+    qlocs = h_q.data();
+  }
   for (int64_t j = 0; j < 2 * q; ++j)
     if (!is_finite(qlocs[j])) return fail(PCV_ERR_INVALID, "non-finite query location");
   if (!p->factored) return fail(PCV_ERR_STATE, "pcv_predict called before pcv_factor");
-  return pcv::predict_impl(p, q, qlocs, mean, var, obs_noise, owner);
+  return pcv::predict_impl(p, q, qlocs, mean, var, obs_noise, owner, dev);
 }
 
 namespace {

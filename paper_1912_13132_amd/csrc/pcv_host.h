@@ -139,7 +139,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t n_theta, const pcv_theta* the
 pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local);
 pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta, int32_t* status);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
-                        int32_t obs_noise, int32_t* owner);
+                        int32_t obs_noise, int32_t* owner, bool dev_out = false);
 pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,
                          int32_t n_slots);
 pcv_status server_submit_predict(pcv_server* s, int64_t q, const double* ql, double* mean, double* var,

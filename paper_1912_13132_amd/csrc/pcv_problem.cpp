@@ -1029,12 +1029,12 @@ pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta,
 }
 
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* ql, double* mean, double* var,
-                        int32_t obs_noise, int32_t* owner_out) {
+                        int32_t obs_noise, int32_t* owner_out, bool dev_out) {
   HIPCHK(hipSetDevice(p->device));
   if (q == 0) return PCV_OK;
   std::vector<int32_t> owner(q);
   route(p, q, ql, owner.data());
-  if (owner_out) std::copy(owner.begin(), owner.end(), owner_out);
+  if (owner_out && !dev_out) std::copy(owner.begin(), owner.end(), owner_out);
   KrigePlan P;
   const int32_t flag = (var ? KRIGE_VAR : 0) | (obs_noise ? KRIGE_OBS_NOISE : 0);
   plan_krige(p, q, ql, owner.data(), nullptr, flag, P);
@@ -1063,8 +1063,11 @@ pcv_status predict_impl(pcv_problem* p, int64_t q, const double* ql, double* mea
   if (e == hipSuccess)
     e = launch_krige(p->stream, p->d_desc_fact, p->d_theta_fact, d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
                      p->d_Invf, p->d_alpha_fact, d_qx, d_qy, d_qorig, d_qflag, d_W, d_mean, d_var);
-  if (e == hipSuccess) e = hipMemcpyAsync(mean, d_mean, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
-  if (e == hipSuccess && var) e = hipMemcpyAsync(var, d_var, sizeof(double) * q, hipMemcpyDeviceToHost, p->stream);
+  const hipMemcpyKind out_kind = dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (e == hipSuccess) e = hipMemcpyAsync(mean, d_mean, sizeof(double) * q, out_kind, p->stream);
+  if (e == hipSuccess && var) e = hipMemcpyAsync(var, d_var, sizeof(double) * q, out_kind, p->stream);
+  if (e == hipSuccess && owner_out && dev_out)
+    e = hipMemcpyAsync(owner_out, owner.data(), sizeof(int32_t) * q, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   for (void* b : {(void*)d_qx, (void*)d_qy, (void*)d_mean, (void*)d_var, (void*)d_W, (void*)d_qorig,
                   (void*)d_qflag, (void*)d_items})

@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
                 ("refine_tol", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("profile", ctypes.c_int32),
                 ("debug_flags", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("inputs_on_device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class EvalReport(ctypes.Structure):
@@ -150,6 +150,21 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def _is_device_tensor(a):
+    return getattr(a, "is_cuda", False) is True
+
+
+def _dev(a, dtype, device):
+    """A contiguous torch tensor of the given dtype on the device (no copy
+    when it already is one)."""
+    import torch
+    return torch.as_tensor(a, dtype=dtype, device=device).contiguous()
+
+
+def _dptr(t, ctype):
+    return ctypes.cast(ctypes.c_void_p(t.data_ptr()), ctypes.POINTER(ctype))
+
+
 def _stream_handle(stream):
     if stream is None:
         return None
@@ -210,15 +225,29 @@ class Problem:
     def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
                  prec="mixed", max_refine=1, refine_tol=1e-4, stream=None, mem_cap=0,
                  profile=False, debug_flags=0, graph=True):
+        """Arrays are numpy-like (host) or, when locs is a torch tensor on the
+        GPU, torch tensors on that device (the library's inputs_on_device
+        option); predict then takes and returns device tensors too."""
         L = lib()
-        self._locs = _as(locs, np.float64).reshape(-1, 2)
-        self._y = _as(y, np.float64)
-        self._tp = _as(train_ptr, np.int64)
-        self._ti = _as(train_idx, np.int32)
-        self._vp = _as(val_ptr, np.int64)
-        self._vi = _as(val_idx, np.int32)
-        self._rect = None if core_rect is None else _as(core_rect, np.float64).reshape(-1, 4)
-        self.S = int(self._tp.shape[0] - 1)
+        self.on_device = _is_device_tensor(locs)
+        if self.on_device:
+            import torch
+            self._device = locs.device
+            conv = lambda a, dt: _dev(a, dt, self._device)
+            f64, i64, i32 = torch.float64, torch.int64, torch.int32
+            ptr = _dptr
+        else:
+            conv = _as
+            f64, i64, i32 = np.float64, np.int64, np.int32
+            ptr = _ptr
+        locs_ = conv(locs, f64).reshape(-1, 2)
+        y_ = conv(y, f64)
+        tp_ = conv(train_ptr, i64)
+        ti_ = conv(train_idx, i32)
+        vp_ = conv(val_ptr, i64)
+        vi_ = conv(val_idx, i32)
+        rect_ = None if core_rect is None else conv(core_rect, f64).reshape(-1, 4)
+        self.S = int(tp_.shape[0] - 1)
         opt = Options()
         L.pcv_default_options(ctypes.byref(opt))
         opt.prec = PREC_MIXED if prec == "mixed" else PREC_FP64
@@ -229,14 +258,15 @@ class Problem:
         opt.profile = 1 if profile else 0
         opt.debug_flags = int(debug_flags)
         opt.graph = 1 if graph else 0
+        opt.inputs_on_device = 1 if self.on_device else 0
         self.prec = prec
         h = ctypes.c_void_p()
         _check(L.pcv_problem_create(
-            ctypes.byref(h), self._locs.shape[0], _ptr(self._locs, ctypes.c_double),
-            _ptr(self._y, ctypes.c_double), self.S, _ptr(self._tp, ctypes.c_int64),
-            _ptr(self._ti, ctypes.c_int32), _ptr(self._vp, ctypes.c_int64),
-            _ptr(self._vi, ctypes.c_int32),
-            None if self._rect is None else _ptr(self._rect, ctypes.c_double), ctypes.byref(opt)))
+            ctypes.byref(h), locs_.shape[0], ptr(locs_, ctypes.c_double),
+            ptr(y_, ctypes.c_double), self.S, ptr(tp_, ctypes.c_int64),
+            ptr(ti_, ctypes.c_int32), ptr(vp_, ctypes.c_int64),
+            ptr(vi_, ctypes.c_int32),
+            None if rect_ is None else ptr(rect_, ctypes.c_double), ctypes.byref(opt)))
         self._h = h
 
     @classmethod
@@ -314,6 +344,20 @@ class Problem:
         _check(lib().pcv_factor_local(self._handle(), arr))
 
     def predict(self, q, want_var=True, obs_noise=False):
+        if self.on_device:
+            import torch
+            q = _dev(q, torch.float64, self._device).reshape(-1, 2)
+            nq = q.shape[0]
+            mean = torch.zeros(nq, dtype=torch.float64, device=self._device)
+            var = torch.zeros(nq, dtype=torch.float64, device=self._device) if want_var else None
+            owner = torch.zeros(nq, dtype=torch.int32, device=self._device)
+            _check(lib().pcv_predict(self._handle(), nq, _dptr(q, ctypes.c_double),
+                                     _dptr(mean, ctypes.c_double),
+                                     None if var is None else _dptr(var, ctypes.c_double),
+                                     1 if obs_noise else 0, _dptr(owner, ctypes.c_int32)))
+            return mean, var, owner
+        if _is_device_tensor(q):
+            q = q.cpu().numpy()
         q = _as(q, np.float64).reshape(-1, 2)
         nq = q.shape[0]
         mean = np.zeros(nq)
