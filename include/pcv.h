@@ -128,6 +128,17 @@ typedef struct {
    * error ~1e-6 of |log det|); the quadratic term uses the refined alpha. */
   double neg2loglik;              /* sum of -2 l_i                                  */
   double* per_subset_neg2loglik;  /* optional out [S] (0 for skipped subsets)       */
+  /* Schedule (pcv_eval).  When there are more evaluated subsets than compute
+   * units and not a whole number of rounds of them, the largest
+   * n_factor_first subsets are factored first (whole rounds) and the rest
+   * beside their solves.  When profiling, ms_factor is that first
+   * factorisation launch alone, ms_solve / ms_refine / ms_predict the first
+   * group's later phases and ms_factor_all the factorisation of every subset
+   * on its stream.  With one group n_factor_first = S evaluated subsets and
+   * ms_factor_all = ms_factor. */
+  int32_t n_factor_first;
+  int32_t pad1;
+  double ms_factor_all;
 } pcv_eval_report;
 
 typedef struct pcv_problem pcv_problem;

@@ -43,6 +43,15 @@ struct pcv_batch {
   pcv_batch_plan plans[2];
 };
 
+// A contiguous group of order_eval and its slices of the item lists: subsets
+// order_eval[o0, o0 + cnt), row and tile items [r0, r0 + nr), validation
+// items [v0, v0 + nv).
+struct pcv_group {
+  int32_t o0 = 0, cnt = 0;
+  int32_t r0 = 0, nr = 0;
+  int32_t v0 = 0, nv = 0;
+};
+
 struct pcv_problem {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -56,7 +65,8 @@ struct pcv_problem {
   std::vector<int32_t> order_eval;  // active subsets, largest n^3 first
   std::vector<int32_t> order_all;   // subsets with >= 1 training point, largest first
   std::vector<int2> row_items_eval; // (subset, 64-row block) over order_eval
-  std::vector<int2> tile_items;     // (subset, row block I), by decreasing I (residual tiles)
+  std::vector<int2> tile_items;     // (subset, row block I), by decreasing I within each
+                                    // group of the schedule (residual tiles)
   std::vector<int2> val_items;      // (subset, 64-point validation block)
   std::vector<double> core_rect;    // S x 4, empty when not given
   pcv_router router;
@@ -68,6 +78,23 @@ struct pcv_problem {
   int32_t max_train = 0;
   int32_t max_npad = 0;
   int32_t n_active = 0;
+  // Evaluation schedule.  g_all covers every evaluated subset; groups split
+  // order_eval into consecutive groups of whole rounds of one factorisation
+  // work-group per compute unit (the last group holds the remainder).  The
+  // factorisations run group after group on the problem's stream; each
+  // group's solves, refinement and kriging follow on one of two further
+  // streams, beside the next group's factorisation, so that the remainder
+  // group does not leave most compute units idle.
+  // The post streams are made at the first evaluation that uses them.  A
+  // problem served by a pcv_server evaluates on its one stream (served), so
+  // that the server's kriging streams keep hardware queues of their own.
+  pcv_group g_all;
+  std::vector<pcv_group> groups;
+  bool served = false;
+  int32_t n_cu = 0;                 // compute units of the device
+  hipStream_t post_stream[2] = {};
+  std::vector<hipEvent_t> ev_fact;
+  hipEvent_t ev_post[2] = {};
 
   // device copies
   pcv::SubsetDesc* d_desc = nullptr;
@@ -138,6 +165,9 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t n_theta, const pcv_theta* the
                            pcv_eval_report* rep);
 pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local);
 pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta, int32_t* status);
+// Single-stream evaluation schedule while a server holds the problem (on)
+// or the two-stream schedule again (off); drops the captured evaluation.
+pcv_status set_served(pcv_problem* p, bool on);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
                         int32_t obs_noise, int32_t* owner, bool dev_out = false);
 pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,

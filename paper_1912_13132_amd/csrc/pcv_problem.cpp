@@ -289,13 +289,38 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   p->n_active = (int32_t)act_ids.size();
   p->order_eval = lpt_order(p->desc, act_ids);
   p->order_all = lpt_order(p->desc, all_ids);
-  for (int32_t i : p->order_eval) {
-    for (int rb = 0; rb < p->desc[i].npad / TB; ++rb) p->row_items_eval.push_back(make_int2(i, rb));
-    for (int vb = 0; vb < (p->desc[i].m + 63) / 64; ++vb) p->val_items.push_back(make_int2(i, vb));
+  // schedule groups: whole rounds of the largest subsets, then the rest
+  int n_cu = 0;
+  HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+  p->n_cu = n_cu;
+  std::vector<int32_t> bounds{0};
+  if (n_cu > 0 && p->n_active > n_cu && p->n_active % n_cu != 0) {
+    bounds.push_back(p->n_active / n_cu * n_cu);
   }
+  bounds.push_back(p->n_active);
+  for (size_t g = 0; g + 1 < bounds.size(); ++g) {
+    pcv_group G;
+    G.o0 = bounds[g];
+    G.cnt = bounds[g + 1] - bounds[g];
+    G.r0 = (int32_t)p->row_items_eval.size();
+    G.v0 = (int32_t)p->val_items.size();
+    for (int32_t k = G.o0; k < G.o0 + G.cnt; ++k) {
+      const int32_t i = p->order_eval[k];
+      for (int rb = 0; rb < p->desc[i].npad / TB; ++rb) p->row_items_eval.push_back(make_int2(i, rb));
+      for (int vb = 0; vb < (p->desc[i].m + 63) / 64; ++vb) p->val_items.push_back(make_int2(i, vb));
+    }
+    G.nr = (int32_t)p->row_items_eval.size() - G.r0;
+    G.nv = (int32_t)p->val_items.size() - G.v0;
+    p->groups.push_back(G);
+  }
+  p->g_all.cnt = p->n_active;
+  p->g_all.nr = (int32_t)p->row_items_eval.size();
+  p->g_all.nv = (int32_t)p->val_items.size();
+  // residual tiles: within each group, largest row block first
   p->tile_items = p->row_items_eval;
-  std::stable_sort(p->tile_items.begin(), p->tile_items.end(),
-                   [](const int2& a, const int2& b) { return a.y > b.y; });
+  for (const pcv_group& G : p->groups)
+    std::stable_sort(p->tile_items.begin() + G.r0, p->tile_items.begin() + G.r0 + G.nr,
+                     [](const int2& a, const int2& b) { return a.y > b.y; });
 
   // per-subset panels, centred on the subset's training centroid (FP64)
   std::vector<double> tx(offT), ty(offT), yT(offT), vx(offV), vy(offV), yV(offV);
@@ -397,6 +422,53 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   return PCV_OK;
 }
 
+namespace {
+
+void drop_post_streams(pcv_problem* p) {
+  for (hipEvent_t e : p->ev_fact)
+    if (e) (void)hipEventDestroy(e);
+  p->ev_fact.clear();
+  for (int q = 0; q < 2; ++q) {
+    if (p->ev_post[q]) (void)hipEventDestroy(p->ev_post[q]);
+    if (p->post_stream[q]) {
+      (void)hipStreamSynchronize(p->post_stream[q]);
+      (void)hipStreamDestroy(p->post_stream[q]);
+    }
+    p->ev_post[q] = nullptr;
+    p->post_stream[q] = nullptr;
+  }
+}
+
+pcv_status ensure_post_streams(pcv_problem* p) {
+  if (p->post_stream[0]) return PCV_OK;
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(hipStreamCreateWithFlags(&p->post_stream[q], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_post[q], hipEventDisableTiming));
+  }
+  p->ev_fact.assign(p->groups.size(), nullptr);
+  for (auto& e : p->ev_fact) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return PCV_OK;
+}
+
+}  // namespace
+
+pcv_status set_served(pcv_problem* p, bool on) {
+  HIPCHK(hipSetDevice(p->device));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (p->graph_exec[0]) {
+    (void)hipGraphExecDestroy(p->graph_exec[0]);
+    p->graph_exec[0] = nullptr;
+  }
+  for (auto& pl : p->batch.plans)
+    if (pl.graph) {
+      (void)hipGraphExecDestroy(pl.graph);
+      pl.graph = nullptr;
+    }
+  drop_post_streams(p);
+  p->served = on;
+  return PCV_OK;
+}
+
 void problem_free(pcv_problem* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
@@ -414,6 +486,7 @@ void problem_free(pcv_problem* p) {
   if (p->h_nbad) (void)hipHostFree(p->h_nbad);
   if (p->events)
     for (auto& e : p->ev) (void)hipEventDestroy(e);
+  drop_post_streams(p);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
@@ -443,48 +516,80 @@ namespace {
 // of the first six.
 constexpr int N_PHASES = 7;
 
-pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, int sweeps) {
+// Subsets per factorisation launch: one launch, or for a served problem
+// launches of one work-group per compute unit.  A served problem's
+// evaluation runs launch by launch with the host waiting for each (the
+// server's kriging streams may share its hardware queue, whose work runs in
+// order), so a kriging batch waits behind one launch at most, and a
+// factorisation launch lasts about one work-group's time.
+int32_t factor_chunk(const pcv_problem* p, int32_t cnt) {
+  return p->served && p->n_cu > 0 ? std::min(cnt, p->n_cu) : std::max(cnt, 1);
+}
+
+pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, int sweeps,
+                         const pcv_group& G) {
   Launch Lc{st, p->d_desc, p->d_theta};
+  const int32_t* order = p->d_order_eval + G.o0;
+  const int32_t cnt = G.cnt;
+  // a served problem's evaluation waits for each launch before the next, so
+  // that a kriging batch sharing its hardware queue never waits behind more
+  // than one launch
+#define PACE()                                       \
+  do {                                               \
+    if (p->served) HIPCHK(hipStreamSynchronize(st)); \
+  } while (0)
   switch (phase) {
     case 0:
       HIPCHK(hipMemcpyAsync(p->d_theta, p->h_theta, sizeof(ThetaDev), hipMemcpyHostToDevice, st));
       break;
     case 1:
-      if (mixed)
-        HIPCHK(launch_potrf_f32(Lc, p->d_order_eval, p->n_active, p->d_px32, p->d_py32, p->d_L32, p->d_Inv,
-                                p->d_logdet, p->d_status));
-      else
-        HIPCHK(launch_potrf_f64(Lc, p->d_order_eval, p->n_active, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
-                                p->d_logdet, p->d_status));
+      for (int32_t c0 = 0; c0 < cnt; c0 += factor_chunk(p, cnt)) {
+        const int32_t c = std::min(factor_chunk(p, cnt), cnt - c0);
+        if (mixed)
+          HIPCHK(launch_potrf_f32(Lc, order + c0, c, p->d_px32, p->d_py32, p->d_L32, p->d_Inv, p->d_logdet,
+                                  p->d_status));
+        else
+          HIPCHK(launch_potrf_f64(Lc, order + c0, c, p->d_px64, p->d_py64, p->d_L64, p->d_Inv, p->d_logdet,
+                                  p->d_status));
+        PACE();
+      }
       break;
     case 2:
       if (mixed) {
-        HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_yT,
+        HIPCHK(launch_trsv_fwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_yT,
                                    nullptr, p->d_z, nullptr));
-        HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
+        PACE();
+        HIPCHK(launch_trsv_bwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
                                    p->d_alpha, nullptr));
+        PACE();
       } else {
-        HIPCHK(launch_trsv_fwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_yT,
+        HIPCHK(launch_trsv_fwd_f64(Lc, order, cnt, p->max_npad, p->d_L64, p->d_Inv, p->d_yT,
                                    nullptr, p->d_z, nullptr));
-        HIPCHK(launch_trsv_bwd_f64(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L64, p->d_Inv, p->d_z,
+        PACE();
+        HIPCHK(launch_trsv_bwd_f64(Lc, order, cnt, p->max_npad, p->d_L64, p->d_Inv, p->d_z,
                                    p->d_alpha, nullptr));
+        PACE();
       }
       break;
     case 3:
       for (int it = 0; it < sweeps; ++it) {
-        HIPCHK(launch_residual(Lc, p->d_tile_items, (int)p->tile_items.size(), p->d_row_items,
-                               (int)p->row_items_eval.size(), p->d_tx, p->d_ty, p->d_yT, p->d_alpha, p->d_rrow,
-                               p->d_pcol, p->d_r));
-        HIPCHK(launch_trsv_fwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, nullptr,
+        HIPCHK(launch_residual(Lc, p->d_tile_items + G.r0, G.nr, p->d_row_items + G.r0, G.nr, p->d_tx, p->d_ty,
+                               p->d_yT, p->d_alpha, p->d_rrow, p->d_pcol, p->d_r));
+        PACE();
+        HIPCHK(launch_trsv_fwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, nullptr,
                                    p->d_r, p->d_z, p->d_rhs2));
-        HIPCHK(launch_trsv_bwd_f32(Lc, p->d_order_eval, p->n_active, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
+        PACE();
+        HIPCHK(launch_trsv_bwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
                                    p->d_x, p->d_alpha));
+        PACE();
       }
       break;
     case 4:
-      HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,
+      HIPCHK(launch_predict_val(Lc, p->d_val_items + G.v0, G.nv, p->d_tx, p->d_ty, p->d_vx,
                                 p->d_vy, p->d_yV, p->d_alpha, p->d_yhat, p->d_err));
-      HIPCHK(launch_quad(st, p->d_desc, p->d_order_eval, p->n_active, p->d_yT, p->d_alpha, p->d_quad));
+      PACE();
+      HIPCHK(launch_quad(st, p->d_desc, order, cnt, p->d_yT, p->d_alpha, p->d_quad));
+      PACE();
       break;
     case 5:
       HIPCHK(launch_reduce(st, p->d_desc, p->S, 1, p->d_err, p->d_status, p->d_active,
@@ -498,18 +603,61 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
   }
   return PCV_OK;
 }
+#undef PACE
 
-// Capture phases [ph0, ph1) on a private stream (so that the caller's stream
-// may be the null stream) and instantiate them as one graph.
-pcv_status capture_phases(pcv_problem* p, int ph0, int ph1, bool mixed, int sweeps, hipGraphExec_t* out) {
-  hipStream_t cs = nullptr;
+// The whole evaluation on st.  With several schedule groups the
+// factorisations run group after group on st and each group's later phases
+// on post stream k % 2 once its factorisation is done; the post streams are
+// joined back into st before the reduction.
+int n_groups(const pcv_problem* p) { return p->served ? 1 : (int)p->groups.size(); }
+
+pcv_status enqueue_all(pcv_problem* p, hipStream_t st, const hipStream_t* ps, bool mixed, int sweeps) {
+  pcv_status s = PCV_OK;
+  const int K = n_groups(p);
+  if (K <= 1) {
+    for (int ph = 0; ph < N_PHASES && s == PCV_OK; ++ph) s = enqueue_phase(p, st, ph, mixed, sweeps, p->g_all);
+    return s;
+  }
+  if ((s = enqueue_phase(p, st, 0, mixed, sweeps, p->g_all)) != PCV_OK) return s;
+  for (int k = 0; k < K; ++k) {
+    if ((s = enqueue_phase(p, st, 1, mixed, sweeps, p->groups[k])) != PCV_OK) return s;
+    HIPCHK(hipEventRecord(p->ev_fact[k], st));
+  }
+  for (int k = 0; k < K; ++k) {
+    hipStream_t q = ps[k & 1];
+    HIPCHK(hipStreamWaitEvent(q, p->ev_fact[k], 0));
+    for (int ph = 2; ph <= 4 && s == PCV_OK; ++ph) s = enqueue_phase(p, q, ph, mixed, sweeps, p->groups[k]);
+    if (s != PCV_OK) return s;
+  }
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(hipEventRecord(p->ev_post[q], ps[q]));
+    HIPCHK(hipStreamWaitEvent(st, p->ev_post[q], 0));
+  }
+  for (int ph = 5; ph < N_PHASES && s == PCV_OK; ++ph) s = enqueue_phase(p, st, ph, mixed, sweeps, p->g_all);
+  return s;
+}
+
+// Capture the whole evaluation on private streams, so that the caller's
+// stream may be the null stream, and instantiate it as one graph.
+pcv_status capture_eval(pcv_problem* p, bool mixed, int sweeps, hipGraphExec_t* out) {
+  hipStream_t cs = nullptr, cps[2] = {};
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipSuccess;
+  if (n_groups(p) > 1) {
+    e = hipStreamCreateWithFlags(&cps[0], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cps[1], hipStreamNonBlocking);
+  }
+  if (e != hipSuccess) {
+    for (hipStream_t x : {cs, cps[0], cps[1]})
+      if (x) (void)hipStreamDestroy(x);
+    return fail(PCV_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  }
   hipGraph_t g = nullptr;
   pcv_status s = PCV_OK;
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) s = fail(PCV_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   if (e == hipSuccess) {
-    for (int ph = ph0; ph < ph1 && s == PCV_OK; ++ph) s = enqueue_phase(p, cs, ph, mixed, sweeps);
+    s = enqueue_all(p, cs, cps, mixed, sweeps);
     e = hipStreamEndCapture(cs, &g);
     if (s == PCV_OK && e != hipSuccess) s = fail(PCV_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   }
@@ -521,40 +669,69 @@ pcv_status capture_phases(pcv_problem* p, int ph0, int ph1, bool mixed, int swee
     }
   }
   if (g) (void)hipGraphDestroy(g);
+  for (hipStream_t x : {cps[1], cps[0]})
+    if (x) (void)hipStreamDestroy(x);
   (void)hipStreamDestroy(cs);
   return s;
 }
 
-// Enqueue one theta-evaluation on the problem's stream: eagerly, as one
-// graph, or (when profiling with graphs) as one graph per phase with the
-// phase events recorded between them.
-pcv_status enqueue_eval(pcv_problem* p, bool mixed, int sweeps) {
+// The schedule of enqueue_all launched eagerly with timing events: ev[0]
+// after the theta upload, ev[1] after the first group's factorisation, ev[7]
+// after the last group's (all on the factorisation stream); ev[2], ev[3],
+// ev[4] after the first group's solves, refinement and kriging (on its post
+// stream); ev[6] after the join and ev[5] after the reduction.
+pcv_status enqueue_profiled(pcv_problem* p, bool mixed, int sweeps) {
   hipStream_t st = p->stream;
-  const bool ev = p->events;
-  if (!p->opt.graph) {
-    for (int ph = 0; ph < N_PHASES; ++ph) {
-      pcv_status s = enqueue_phase(p, st, ph, mixed, sweeps);
-      if (s != PCV_OK) return s;
-      if (ev && ph < 6) HIPCHK(hipEventRecord(p->ev[ph], st));
-    }
-    return PCV_OK;
+  const int K = n_groups(p);
+  const pcv_group& G0 = K > 1 ? p->groups[0] : p->g_all;
+  pcv_status s = enqueue_phase(p, st, 0, mixed, sweeps, p->g_all);
+  if (s != PCV_OK) return s;
+  HIPCHK(hipEventRecord(p->ev[0], st));
+  if ((s = enqueue_phase(p, st, 1, mixed, sweeps, G0)) != PCV_OK) return s;
+  HIPCHK(hipEventRecord(p->ev[1], st));
+  if (K > 1) HIPCHK(hipEventRecord(p->ev_fact[0], st));
+  for (int k = 1; k < K; ++k) {
+    if ((s = enqueue_phase(p, st, 1, mixed, sweeps, p->groups[k])) != PCV_OK) return s;
+    HIPCHK(hipEventRecord(p->ev_fact[k], st));
   }
-  if (!ev) {
-    if (!p->graph_exec[0]) {
-      pcv_status s = capture_phases(p, 0, N_PHASES, mixed, sweeps, &p->graph_exec[0]);
-      if (s != PCV_OK) return s;
-    }
-    HIPCHK(hipGraphLaunch(p->graph_exec[0], st));
-    return PCV_OK;
+  HIPCHK(hipEventRecord(p->ev[7], st));
+  hipStream_t q0 = K > 1 ? p->post_stream[0] : st;
+  if (K > 1) HIPCHK(hipStreamWaitEvent(q0, p->ev_fact[0], 0));
+  for (int ph = 2; ph <= 4; ++ph) {
+    if ((s = enqueue_phase(p, q0, ph, mixed, sweeps, G0)) != PCV_OK) return s;
+    HIPCHK(hipEventRecord(p->ev[ph], q0));
   }
-  for (int ph = 0; ph < N_PHASES; ++ph) {
-    if (!p->graph_exec[1 + ph]) {
-      pcv_status s = capture_phases(p, ph, ph + 1, mixed, sweeps, &p->graph_exec[1 + ph]);
-      if (s != PCV_OK) return s;
-    }
-    HIPCHK(hipGraphLaunch(p->graph_exec[1 + ph], st));
-    if (ph < 6) HIPCHK(hipEventRecord(p->ev[ph], st));
+  for (int k = 1; k < K; ++k) {
+    hipStream_t q = p->post_stream[k & 1];
+    HIPCHK(hipStreamWaitEvent(q, p->ev_fact[k], 0));
+    for (int ph = 2; ph <= 4 && s == PCV_OK; ++ph) s = enqueue_phase(p, q, ph, mixed, sweeps, p->groups[k]);
+    if (s != PCV_OK) return s;
   }
+  if (K > 1)
+    for (int q = 0; q < 2; ++q) {
+      HIPCHK(hipEventRecord(p->ev_post[q], p->post_stream[q]));
+      HIPCHK(hipStreamWaitEvent(st, p->ev_post[q], 0));
+    }
+  HIPCHK(hipEventRecord(p->ev[6], st));
+  if ((s = enqueue_phase(p, st, 5, mixed, sweeps, p->g_all)) != PCV_OK) return s;
+  HIPCHK(hipEventRecord(p->ev[5], st));
+  return enqueue_phase(p, st, 6, mixed, sweeps, p->g_all);
+}
+
+// Enqueue one theta-evaluation on the problem's stream: as one graph
+// (default), eagerly, or eagerly with timing events when profiling.
+pcv_status enqueue_eval(pcv_problem* p, bool mixed, int sweeps) {
+  if (n_groups(p) > 1) {
+    pcv_status s = ensure_post_streams(p);
+    if (s != PCV_OK) return s;
+  }
+  if (p->events) return enqueue_profiled(p, mixed, sweeps);
+  if (!p->opt.graph || p->served) return enqueue_all(p, p->stream, p->post_stream, mixed, sweeps);
+  if (!p->graph_exec[0]) {
+    pcv_status s = capture_eval(p, mixed, sweeps, &p->graph_exec[0]);
+    if (s != PCV_OK) return s;
+  }
+  HIPCHK(hipGraphLaunch(p->graph_exec[0], p->stream));
   return PCV_OK;
 }
 
@@ -656,6 +833,8 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
       rep->neg2loglik = sum + comp;
     }
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
+    rep->ms_factor_all = 0.0;
+    rep->n_factor_first = n_groups(p) > 1 ? p->groups[0].cnt : p->n_active;
     if (p->events) {
       float ms;
       HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
@@ -666,8 +845,10 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
       rep->ms_refine = ms;
       HIPCHK(hipEventElapsedTime(&ms, p->ev[3], p->ev[4]));
       rep->ms_predict = ms;
-      HIPCHK(hipEventElapsedTime(&ms, p->ev[4], p->ev[5]));
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[6], p->ev[5]));
       rep->ms_reduce = ms;
+      HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[7]));
+      rep->ms_factor_all = ms;
     }
     rep->seconds = now_s() - t0;
   }
@@ -792,33 +973,53 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
   pcv_batch& b = p->batch;
   Launch Lc{st, b.d_desc, b.d_theta};
   const int nb = pl.nb;
+  // a served problem waits for each launch before the next, so that a
+  // kriging batch sharing its hardware queue waits behind one launch at most
+  auto pace = [&]() { return p->served ? hipStreamSynchronize(st) : hipSuccess; };
+  const int32_t chunk = factor_chunk(p, pl.n_order);
   HIPCHK(hipMemcpyAsync(b.d_theta, b.h_theta, sizeof(ThetaDev) * nb, hipMemcpyHostToDevice, st));
   if (ev) HIPCHK(hipEventRecord(p->ev[0], st));
   if (mixed) {
     float* L = (float*)b.d_L;
-    HIPCHK(launch_potrf_f32(Lc, pl.d_order, pl.n_order, p->d_px32, p->d_py32, L, b.d_Inv, b.d_logdet, b.d_status));
+    for (int32_t c0 = 0; c0 < pl.n_order; c0 += chunk) {
+      HIPCHK(launch_potrf_f32(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0), p->d_px32, p->d_py32, L,
+                              b.d_Inv, b.d_logdet, b.d_status));
+      HIPCHK(pace());
+    }
     if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
     HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));
+    HIPCHK(pace());
     HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_alpha, nullptr));
+    HIPCHK(pace());
     if (ev) HIPCHK(hipEventRecord(p->ev[2], st));
     for (int it = 0; it < sweeps; ++it) {
       HIPCHK(launch_residual(Lc, pl.d_tile_items, pl.n_tile, pl.d_row_items, pl.n_row, p->d_tx, p->d_ty, p->d_yT,
                              b.d_alpha, b.d_rrow, b.d_pcol, b.d_r));
+      HIPCHK(pace());
       HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, nullptr, b.d_r, b.d_z,
                                  b.d_rhs2));
+      HIPCHK(pace());
       HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_x, b.d_alpha));
+      HIPCHK(pace());
     }
   } else {
     double* L = (double*)b.d_L;
-    HIPCHK(launch_potrf_f64(Lc, pl.d_order, pl.n_order, p->d_px64, p->d_py64, L, b.d_Inv, b.d_logdet, b.d_status));
+    for (int32_t c0 = 0; c0 < pl.n_order; c0 += chunk) {
+      HIPCHK(launch_potrf_f64(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0), p->d_px64, p->d_py64, L,
+                              b.d_Inv, b.d_logdet, b.d_status));
+      HIPCHK(pace());
+    }
     if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
     HIPCHK(launch_trsv_fwd_f64(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));
+    HIPCHK(pace());
     HIPCHK(launch_trsv_bwd_f64(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_alpha, nullptr));
+    HIPCHK(pace());
     if (ev) HIPCHK(hipEventRecord(p->ev[2], st));
   }
   if (ev) HIPCHK(hipEventRecord(p->ev[3], st));
   HIPCHK(launch_predict_val(Lc, pl.d_val_items, pl.n_val, p->d_tx, p->d_ty, p->d_vx, p->d_vy, p->d_yV, b.d_alpha,
                             b.d_yhat, b.d_err));
+  HIPCHK(pace());
   if (ev) HIPCHK(hipEventRecord(p->ev[4], st));
   HIPCHK(launch_reduce(st, b.d_desc, p->S, nb, b.d_err, b.d_status, p->d_active, sweeps > 0 ? b.d_rhs2 : nullptr,
                        p->d_ynorm2, p->opt.refine_tol, b.d_sspe, b.d_total, b.d_nbad));
@@ -836,6 +1037,8 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
   HIPCHK(hipSetDevice(p->device));
   if (rep) {
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
+    rep->ms_factor_all = 0.0;
+    rep->n_factor_first = p->n_active;
     rep->n_fallback_fp64 = 0;
     rep->n_val = p->n_val_total;
     rep->n_subsets_used = p->n_active;
@@ -860,6 +1063,8 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
         rep->ms_refine += r1.ms_refine;
         rep->ms_predict += r1.ms_predict;
         rep->ms_reduce += r1.ms_reduce;
+        rep->ms_factor_all += r1.ms_factor_all;
+        rep->n_factor_first = r1.n_factor_first;
         rep->n_fallback_fp64 += r1.n_fallback_fp64;
       }
     }
@@ -884,7 +1089,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
     pcv_batch_plan* pl = nullptr;
     if ((s = batch_plan(p, nb, &pl)) != PCV_OK) return s;
     const bool ev = p->events && rep;
-    if (p->opt.graph && !ev) {
+    if (p->opt.graph && !ev && !p->served) {
       if (!pl->graph) {
         hipStream_t cs = nullptr;
         HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -912,6 +1117,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
       float ms[5];
       for (int k = 0; k < 5; ++k) HIPCHK(hipEventElapsedTime(&ms[k], p->ev[k], p->ev[k + 1]));
       rep->ms_factor += ms[0];
+      rep->ms_factor_all += ms[0];
       rep->ms_solve += ms[1];
       rep->ms_refine += ms[2];
       rep->ms_predict += ms[3];

@@ -97,6 +97,10 @@ struct pcv_server {
   int64_t w_cap = 0;       // variance scratch doubles per batch
   size_t ws_bytes = 0;     // device bytes of all slots
   std::vector<Slot> slots;
+  // Evaluations run on a stream of the server's own (the problem's stream is
+  // swapped for it while served).
+  hipStream_t eval_stream = nullptr;
+  hipStream_t saved_stream = nullptr;
 
   std::mutex mu;
   std::condition_variable cv_batch;  // batcher: work queued or slot freed
@@ -359,6 +363,12 @@ void free_slots_mem(pcv_server* s) {
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   s->slots.clear();
+  if (s->eval_stream) {
+    (void)hipStreamSynchronize(s->eval_stream);
+    if (s->saved_stream) s->p->stream = s->saved_stream;
+    (void)hipStreamDestroy(s->eval_stream);
+    s->eval_stream = nullptr;
+  }
 }
 
 }  // namespace
@@ -367,6 +377,9 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
                          int32_t n_slots) {
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return fail(PCV_ERR_DEVICE, hipGetErrorString(e));
+  // evaluations of a served problem stay on its one stream
+  pcv_status st0 = set_served(p, true);
+  if (st0 != PCV_OK) return st0;
   pcv_server* s = new pcv_server();
   s->p = p;
   s->max_inflight = max_inflight;
@@ -381,8 +394,15 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
   s->item_cap = s->w_cap / w_item;
   if (s->item_cap < 1) {
     delete s;
+    (void)set_served(p, false);
     return fail(PCV_ERR_INVALID, "mem_budget too small for one kriging item per slot (need " +
                                      std::to_string((w_item * 8 + 64 * 40 * 4) * n_slots) + " bytes)");
+  }
+  e = hipStreamCreateWithFlags(&s->eval_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete s;
+    (void)set_served(p, false);
+    return fail(PCV_ERR_DEVICE, std::string("server stream: ") + hipGetErrorString(e));
   }
   s->slots.resize(n_slots);
   for (Slot& sl : s->slots) {
@@ -410,10 +430,13 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
   if (e != hipSuccess) {
     free_slots_mem(s);
     delete s;
+    (void)set_served(p, false);
     return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,
                 std::string("server workspace: ") + hipGetErrorString(e));
   }
   for (int i = 0; i < n_slots; ++i) s->free_slots.push_back(i);
+  s->saved_stream = p->stream;
+  p->stream = s->eval_stream;
   s->th_batch = std::thread(batcher, s);
   s->th_comp = std::thread(completer, s);
   s->th_eval = std::thread(evaluator, s);
@@ -530,8 +553,9 @@ pcv_status server_destroy(pcv_server* s) {
   for (auto& kv : s->reqs) delete kv.second;
   s->reqs.clear();
   free_slots_mem(s);
+  pcv_problem* p = s->p;
   delete s;
-  return PCV_OK;
+  return set_served(p, false);
 }
 
 }  // namespace pcv

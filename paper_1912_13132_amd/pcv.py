@@ -57,7 +57,8 @@ class EvalReport(ctypes.Structure):
                 ("ms_reduce", ctypes.c_double),
                 ("per_subset_sspe", _c_double_p), ("per_subset_logdet", _c_double_p),
                 ("per_subset_iters", _c_int32_p), ("neg2loglik", ctypes.c_double),
-                ("per_subset_neg2loglik", _c_double_p)]
+                ("per_subset_neg2loglik", _c_double_p), ("n_factor_first", ctypes.c_int32),
+                ("pad1", ctypes.c_int32), ("ms_factor_all", ctypes.c_double)]
 
 
 class ServerReport(ctypes.Structure):
@@ -299,7 +300,7 @@ class Problem:
         rep.per_subset_neg2loglik = _ptr(nll, ctypes.c_double)
         _check(L.pcv_eval(self._handle(), ctypes.byref(th), ctypes.byref(loss), ctypes.byref(rep)))
         d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
-             if not k.startswith("per_subset") and k != "pad0"}
+             if not k.startswith("per_subset") and k not in ("pad0", "pad1")}
         d.update(per_subset_sspe=z, per_subset_logdet=ld, per_subset_iters=it,
                  per_subset_neg2loglik=nll)
         return loss.value, d
@@ -318,7 +319,7 @@ class Problem:
         _check(L.pcv_eval_batch_ex(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double),
                                    ctypes.byref(rep)))
         d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
-             if not k.startswith("per_subset") and k != "pad0"}
+             if not k.startswith("per_subset") and k not in ("pad0", "pad1")}
         return out, d
 
     def eval_grid(self, thetas):

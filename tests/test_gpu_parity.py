@@ -318,3 +318,33 @@ def test_predict_interpolates_without_nugget():
         mean, var, _ = P.predict(locs[::5])
     np.testing.assert_allclose(mean, y[::5], atol=1e-8)
     np.testing.assert_allclose(var, 0.0, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_two_stream_schedule(prec, tol):
+    """More evaluated subsets than compute units and not a whole number of
+    rounds (300 on 256): the remainder's factorisation and solves run on a
+    second stream beside the first group's.  The loss and per-subset values
+    carry the same bits as the single-stream phase-by-phase schedule, in
+    graph replays and eager launches, and match the oracle."""
+    r = _rng(41)
+    sizes_T = list(r.integers(30, 200, size=300))
+    sizes_V = list(r.integers(1, 12, size=300))
+    sizes_V[7] = 0  # a skipped subset among them
+    locs, y, tp, ti, vp, vi = _synthetic(sizes_T, sizes_V, 42)
+    say(f"[case] two-stream schedule prec={prec} S=300")
+    th = pcv.theta(0.3, 0.1)
+    ref = oracle.cv_loss(locs, y, tp, ti, vp, vi, 0, 0.3, 0.1)
+    out = {}
+    for name, kw in (("graph", {}), ("eager", {"graph": False}), ("phases", {"profile": True})):
+        with pcv.Problem(locs, y, tp, ti, vp, vi, prec=prec, **kw) as P:
+            vals = [P.eval(th, report=True) for _ in range(3)]
+        for loss, rep in vals[1:]:
+            assert loss == vals[0][0]
+            np.testing.assert_array_equal(rep["per_subset_sspe"], vals[0][1]["per_subset_sspe"])
+        out[name] = vals[0]
+    for name in ("eager", "phases"):
+        assert out[name][0] == out["graph"][0], name
+        np.testing.assert_array_equal(out[name][1]["per_subset_sspe"], out["graph"][1]["per_subset_sspe"])
+        np.testing.assert_array_equal(out[name][1]["per_subset_logdet"], out["graph"][1]["per_subset_logdet"])
+    assert _rel(out["graph"][0], ref["sspe"]) <= tol
