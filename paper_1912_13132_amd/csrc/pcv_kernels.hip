@@ -10,8 +10,8 @@
 //                   symmetric tiles, fixed-order partial sums)
 //   k_predict_val   kriging predictor eq. (3) at the validation points and
 //                   squared errors of eq. (4), FP64
-//   k_reduce        per-subset SSPE z_i and the sum of eq. (7) / Algorithm 1
-//                   (fixed-order compensated FP64 sums)
+//   k_subset_sspe,  per-subset SSPE z_i and the sum of eq. (7) / Algorithm 1
+//   k_reduce_total  (fixed-order compensated FP64 sums)
 #include <type_traits>
 
 #include "pcv_device.h"
@@ -440,10 +440,13 @@ __global__ __launch_bounds__(256) void k_predict_val(const SubsetDesc* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Per-subset SSPE and the global sum (eq. (7), Algorithm 1's final step).
-// One workgroup; thread t owns subsets t, t+256, ... in index order, sums
-// each subset's errors in order with Neumaier compensation, then the 256
-// partial (hi, lo) pairs are combined by a fixed tree.  The result does not
+// Per-subset SSPE and the global sum (eq. (7), Algorithm 1's final step), in
+// two launches.  k_subset_sspe: one wave per (theta slot, subset); lane l
+// adds errors l, l + 64, ... with Neumaier compensation, then the 64 (hi, lo)
+// pairs are combined by a fixed butterfly (two_sum gives the exact error in
+// either operand order, so every lane ends with the same pair).
+// k_reduce_total: one workgroup per theta slot; thread t adds subsets t,
+// t + 256, ... in index order, then a fixed tree.  The result does not
 // depend on launch order or batch composition.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
@@ -452,15 +455,48 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bb)) + (b - bb);
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ desc, int S,
-                                                const double* __restrict__ err,
-                                                int32_t* __restrict__ status,
-                                                const int32_t* __restrict__ active,
-                                                const double* __restrict__ rhs2,
-                                                const double* __restrict__ ynorm2, double tol2,
-                                                double* __restrict__ per_subset,
-                                                double* __restrict__ out_total,
-                                                int32_t* __restrict__ out_nbad) {
+__global__ __launch_bounds__(256) void k_subset_sspe(const SubsetDesc* __restrict__ desc, int S, int n_desc,
+                                                     const double* __restrict__ err,
+                                                     int32_t* __restrict__ status,
+                                                     const int32_t* __restrict__ active,
+                                                     const double* __restrict__ rhs2,
+                                                     const double* __restrict__ ynorm2, double tol2,
+                                                     double* __restrict__ per_subset) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (k >= n_desc) return;  // the whole wave
+  const int i = k % S;
+  const bool act = active[i] != 0;
+  const SubsetDesc D = desc[k];
+  double hi = 0.0, lo = 0.0;
+  if (act)
+    for (int v = l; v < D.m; v += 64) {
+      double s, e;
+      two_sum(hi, err[D.offE + v], s, e);
+      hi = s;
+      lo += e;
+    }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oh = __shfl_xor(hi, off, 64), ol = __shfl_xor(lo, off, 64);
+    double s, e;
+    two_sum(hi, oh, s, e);
+    hi = s;
+    lo = (lo + ol) + e;
+  }
+  if (l == 0) {
+    per_subset[k] = hi + lo;
+    // a mixed-precision subset whose residual before the last correction
+    // was not small enough is re-run in FP64 like a broken-down one
+    if (act && rhs2 && status[k] == 0 && rhs2[k] > tol2 * ynorm2[i]) status[k] = PCV_STATUS_STAGNATED;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_total(int S, const int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ active,
+                                                      const double* __restrict__ per_subset,
+                                                      double* __restrict__ out_total,
+                                                      int32_t* __restrict__ out_nbad) {
   __shared__ double hi[256], lo[256];
   __shared__ int nb[256];
   const int tid = threadIdx.x;
@@ -469,24 +505,9 @@ __global__ __launch_bounds__(256) void k_reduce(const SubsetDesc* __restrict__ d
   int bad = 0;
   for (int i = tid; i < S; i += 256) {
     const int k = base + i;
-    const SubsetDesc D = desc[k];
-    double zi = 0.0, zc = 0.0;
-    if (active[i]) {
-      for (int v = 0; v < D.m; ++v) {
-        double s, e;
-        two_sum(zi, err[D.offE + v], s, e);
-        zi = s;
-        zc += e;
-      }
-      // a mixed-precision subset whose residual before the last correction
-      // was not small enough is re-run in FP64 like a broken-down one
-      if (rhs2 && status[k] == 0 && rhs2[k] > tol2 * ynorm2[i]) status[k] = PCV_STATUS_STAGNATED;
-      if (status[k]) ++bad;
-    }
-    const double z = zi + zc;
-    per_subset[k] = z;
+    if (active[i] && status[k]) ++bad;
     double s, e;
-    two_sum(th, z, s, e);
+    two_sum(th, per_subset[k], s, e);
     th = s;
     tl += e;
   }
@@ -708,8 +729,11 @@ hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_the
                          int32_t* status, const int32_t* active, const double* rhs2,
                          const double* ynorm2, double tol, double* per_subset, double* out_total,
                          int32_t* out_nbad) {
-  hipLaunchKernelGGL(k_reduce, dim3(n_theta), dim3(256), 0, s, desc, S, err, status, active, rhs2, ynorm2,
-                     tol * tol, per_subset, out_total, out_nbad);
+  const int n_desc = S * n_theta;
+  hipLaunchKernelGGL(k_subset_sspe, dim3((n_desc + 3) / 4), dim3(256), 0, s, desc, S, n_desc, err, status, active,
+                     rhs2, ynorm2, tol * tol, per_subset);
+  hipLaunchKernelGGL(k_reduce_total, dim3(n_theta), dim3(256), 0, s, S, status, active, per_subset, out_total,
+                     out_nbad);
   return hipGetLastError();
 }
 
