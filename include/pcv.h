@@ -248,6 +248,14 @@ pcv_status pcv_problem_info(const pcv_problem* p, int32_t* S, int64_t* nnz_train
 const char* pcv_status_string(pcv_status s);
 const char* pcv_last_error(void);
 
+/* Testing hook for the FP64 device arithmetic of the refinement residual and
+ * the kriging of validation points: on the current device,
+ * e[i] = e^{-t[i]} (t[i] >= 0; t above 740 is taken as 740) and
+ * r[i] = sqrt(x[i]) (x[i] >= 0), for i < n.  Host arrays of n doubles.
+ * Errors: PCV_ERR_INVALID (n < 0, NULL arrays, negative or non-finite
+ * input), PCV_ERR_OOM, PCV_ERR_DEVICE. */
+pcv_status pcv_selftest_math(int64_t n, const double* t, const double* x, double* e, double* r);
+
 /* -------------------------------------------------------- partitioning --
  * The division of Sec. 2.3 / 2.4 (Algorithm 1, steps 2-3) on the device: the
  * input preparation for pcv_problem_create.  Rectangles are (xlo, ylo, xhi,

@@ -135,6 +135,27 @@ const char* pcv_status_string(pcv_status s) {
 
 const char* pcv_last_error(void) { return pcv::g_err.c_str(); }
 
+pcv_status pcv_selftest_math(int64_t n, const double* t, const double* x, double* e, double* r) {
+  pcv::g_err.clear();
+  if (n < 0 || (n > 0 && (!t || !x || !e || !r))) return fail(PCV_ERR_INVALID, "bad arguments");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(t[i] >= 0.0) || !(x[i] >= 0.0) || !is_finite(t[i]) || !is_finite(x[i]))
+      return fail(PCV_ERR_INVALID, "inputs must be finite and >= 0");
+  if (n == 0) return PCV_OK;
+  const size_t bytes = sizeof(double) * (size_t)n;
+  double* d = nullptr;
+  hipError_t err = hipMalloc((void**)&d, 4 * bytes);
+  if (err != hipSuccess) return fail(PCV_ERR_OOM, hipGetErrorString(err));
+  if (err == hipSuccess) err = hipMemcpy(d, t, bytes, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(d + n, x, bytes, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = pcv::launch_math_check(nullptr, n, d, d + n, d + 2 * n, d + 3 * n);
+  if (err == hipSuccess) err = hipMemcpy(e, d + 2 * n, bytes, hipMemcpyDeviceToHost);
+  if (err == hipSuccess) err = hipMemcpy(r, d + 3 * n, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (err != hipSuccess) return fail(PCV_ERR_DEVICE, hipGetErrorString(err));
+  return PCV_OK;
+}
+
 pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs, const double* y,
                               int32_t S, const int64_t* train_ptr, const int32_t* train_idx,
                               const int64_t* val_ptr, const int32_t* val_idx, const double* core_rect,

@@ -140,4 +140,7 @@ hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_the
                          int32_t* status, const int32_t* active, const double* rhs2,
                          const double* ynorm2, double tol, double* per_subset_sspe,
                          double* out_total, int32_t* out_nbad);
+// Testing hook: e[i] = e^{-t[i]} and r[i] = sqrt(x[i]) by the FP64 device
+// functions of the residual and the kriging of validation points.
+hipError_t launch_math_check(hipStream_t s, int64_t n, const double* t, const double* x, double* e, double* r);
 }  // namespace pcv

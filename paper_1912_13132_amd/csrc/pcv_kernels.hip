@@ -50,13 +50,56 @@ __device__ __forceinline__ float corr(int cov, float d, float inv_range) {
   const float e = expf(-t);
   return cov == 1 ? (1.0f + t) * e : e;
 }
+// e^{-t}, t >= 0, in FP64.  t is clamped to 740 (e^{-740} < 1e-321: such
+// entries are negligible).  t = k ln 2 + f with k the integer nearest to
+// t / ln 2 and |f| <= ln 2 / 2, ln 2 split into a high part with trailing
+// zero bits (k ln2_hi is exact for |k| < 2^21) and a low part; e^{-f} by its
+// Taylor polynomial of degree 13 (truncation below 1e-17 relative), times
+// 2^{-k}.  No range checks are needed for this argument range.
+__device__ __forceinline__ double exp_neg(double t) {
+  constexpr double LOG2E = 1.4426950408889634074;
+  constexpr double LN2_HI = 6.93147180369123816490e-01;
+  constexpr double LN2_LO = 1.90821492927058770002e-10;
+  t = fmin(t, 740.0);
+  const double k = rint(t * LOG2E);
+  const double g = -fma(-k, LN2_LO, fma(-k, LN2_HI, t));  // -f
+  double p = 1.0 / 6227020800.0;                          // 1 / 13!
+  p = fma(p, g, 1.0 / 479001600.0);
+  p = fma(p, g, 1.0 / 39916800.0);
+  p = fma(p, g, 1.0 / 3628800.0);
+  p = fma(p, g, 1.0 / 362880.0);
+  p = fma(p, g, 1.0 / 40320.0);
+  p = fma(p, g, 1.0 / 5040.0);
+  p = fma(p, g, 1.0 / 720.0);
+  p = fma(p, g, 1.0 / 120.0);
+  p = fma(p, g, 1.0 / 24.0);
+  p = fma(p, g, 1.0 / 6.0);
+  p = fma(p, g, 0.5);
+  p = fma(p, g, 1.0);
+  p = fma(p, g, 1.0);
+  return ldexp(p, -(int)k);
+}
+// sqrt(x), x >= 0, in FP64: the hardware reciprocal square root estimate
+// (relative error about 2^-23), one coupled Newton step for sqrt(x) and
+// 1 / (2 sqrt(x)), then a residual correction.  x is raised to 1e-300
+// first, so that x = 0 gives 1e-150, where e^{-d / theta} is exactly 1.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  x = fmax(x, 1e-300);
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  const double d = fma(-s, s, x);
+  return fma(d, h, s);
+}
 __device__ __forceinline__ double corr(int cov, double d, double inv_range) {
   const double t = d * inv_range;
-  const double e = exp(-t);
+  const double e = exp_neg(t);
   return cov == 1 ? (1.0 + t) * e : e;
 }
 __device__ __forceinline__ float dist(float x, float y) { return sqrtf(x * x + y * y); }
-__device__ __forceinline__ double dist(double x, double y) { return sqrt(x * x + y * y); }
+__device__ __forceinline__ double dist(double x, double y) { return sqrt_pos(x * x + y * y); }
 
 // 16-byte vector of T for global -> LDS staging.
 template <typename T>
@@ -333,9 +376,11 @@ __global__ __launch_bounds__(256, 3) void k_residual_tiles(const SubsetDesc* __r
     for (int u = 0; u < 8; ++u) {
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
+        // rows and columns beyond n carry the first point's coordinates and
+        // alpha = 0, so they add exact zeros to the other side's sums (their
+        // own sums are never read): no mask is needed
         const double dx = xi[u] - xj[v], dy = yi[u] - yj[v];
-        double c = corr(cov, dist(dx, dy), ir);
-        c = (vi[u] && vj[v]) ? c : 0.0;
+        const double c = corr(cov, dist(dx, dy), ir);
         rp[u] += c * aj[v];
         cp[v] += c * ai[u];
       }
@@ -734,6 +779,22 @@ hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_the
                      rhs2, ynorm2, tol * tol, per_subset);
   hipLaunchKernelGGL(k_reduce_total, dim3(n_theta), dim3(256), 0, s, S, status, active, per_subset, out_total,
                      out_nbad);
+  return hipGetLastError();
+}
+
+// Testing hook: exp_neg and sqrt_pos on n values.
+__global__ __launch_bounds__(256) void k_math_check(int64_t n, const double* __restrict__ t,
+                                                    const double* __restrict__ x, double* __restrict__ e,
+                                                    double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    e[i] = exp_neg(t[i]);
+    r[i] = sqrt_pos(x[i]);
+  }
+}
+hipError_t launch_math_check(hipStream_t s, int64_t n, const double* t, const double* x, double* e, double* r) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_math_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, t, x, e, r);
   return hipGetLastError();
 }
 

@@ -119,6 +119,7 @@ def lib():
     L.pcv_part_subsets.argtypes = [ctypes.c_int64, _c_double_p, ctypes.c_int32, _c_double_p, ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_uint8), _c_int32_p, _c_int64_p, _c_int32_p,
                                    _c_int64_p, _c_int32_p]
+    L.pcv_selftest_math.argtypes = [ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p]
     L.pcv_status_string.argtypes = [ctypes.c_int]
     L.pcv_status_string.restype = ctypes.c_char_p
     L.pcv_last_error.argtypes = []
@@ -126,7 +127,7 @@ def lib():
     for f in ("pcv_problem_create", "pcv_eval", "pcv_eval_batch", "pcv_factor", "pcv_predict",
               "pcv_problem_destroy", "pcv_problem_info", "pcv_server_create", "pcv_factor_local",
               "pcv_eval_grid", "pcv_gls", "pcv_eval_batch_ex", "pcv_part_divide", "pcv_part_count",
-              "pcv_part_subsets",
+              "pcv_part_subsets", "pcv_selftest_math",
               "pcv_server_submit_predict", "pcv_server_submit_eval", "pcv_server_wait",
               "pcv_server_stats", "pcv_server_report_get", "pcv_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
@@ -137,6 +138,19 @@ def lib():
 def _check(st):
     if st != PCV_OK:
         raise PcvError(st, lib().pcv_last_error().decode())
+
+
+def selftest_math(t, x):
+    """Testing hook: e^{-t} and sqrt(x) by the device's FP64 functions."""
+    t = _as(t, np.float64)
+    x = _as(x, np.float64)
+    if t.shape != x.shape:
+        raise ValueError("t and x must have the same shape")
+    e = np.zeros_like(t)
+    r = np.zeros_like(x)
+    _check(lib().pcv_selftest_math(t.size, _ptr(t, ctypes.c_double), _ptr(x, ctypes.c_double),
+                                   _ptr(e, ctypes.c_double), _ptr(r, ctypes.c_double)))
+    return e, r
 
 
 def theta(range_, lam, cov=COV_EXP, sigma2=1.0):
