@@ -336,7 +336,9 @@ def main():
     peak = PEAK_FP32_MFMA if a.prec == "mixed" else PEAK_FP64_MFMA
     ach = flops_first / (ms_fac * 1e-3) / 1e12
     src = os.path.join(ROOT, "paper_1912_13132_amd", "csrc", "pcv_potrf.hip")
-    kname = "k_potrf<float>" if a.prec == "mixed" else "k_potrf<double>"
+    # FP32 launches whose largest subset has npad <= 1536 use 256-thread workgroups
+    shape = 256 if a.prec == "mixed" and int(npad[act].max()) <= 1536 else 512
+    kname = f"k_potrf<{'float' if a.prec == 'mixed' else 'double'}, {shape}>"
     out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                        "frac": ach / peak,
                        "traffic": (measured_traffic(src, a.prec, n_first)

@@ -72,7 +72,9 @@ struct Launch {
   const SubsetDesc* desc;
   const ThetaDev* theta;
 };
-hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, const float* cx,
+// max_npad: the largest padded size among the listed subsets (at most 1,536:
+// workgroups of 4 waves, two per compute unit; else 8 waves).
+hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
                             int32_t* status);
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,

@@ -1,11 +1,12 @@
 // Batched blocked Cholesky of the subset matrices M_i = Sigma_i(theta) +
 // lambda I (the (Sigma + lambda I)^{-1} of eq. (3), arXiv:1912.13132), one
-// workgroup of 8 waves per subset, two workgroups per compute unit.
+// workgroup per subset: 8 waves (one workgroup per compute unit) or, for
+// small FP32 subsets, 4 waves with 64-column panels (two per compute unit).
 //
 // Left-looking over column panels of PB columns (PB = 128 for FP32, 64 for
-// FP64).  For every panel J and every chunk of 256 rows at or below the
-// diagonal, each wave keeps the TRANSPOSED chunk C^T (PB x 32) in MFMA
-// accumulators:
+// FP64 and for the small shape).  For every panel J and every chunk of 32
+// rows per wave at or below the diagonal, each wave keeps the TRANSPOSED
+// chunk C^T (PB x 32) in MFMA accumulators:
 //   1. C^T is initialised with the covariance (Sec. 3, exponential or
 //      Matern-3/2) of the chunk rows and panel columns, generated from the
 //      subset's centred coordinates (padded to npad with points at infinity,
@@ -105,16 +106,22 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int NT = 512;   // threads per workgroup (8 waves)
 constexpr int WR = 32;    // chunk rows per wave
 constexpr int NBJ = WR / 16;
-constexpr int RCH = NT / 64 * WR;  // chunk rows (256)
 constexpr int LDD = 65;   // FP64 diagonal array row stride (doubles)
 
-template <typename T>
-struct Smem {
-  static constexpr int PB = Cfg<T>::PB;
+// Workgroup shape: NTH threads (NTH / 64 waves) per subset.  512: panels of
+// Cfg<T>::PB columns and 256-row chunks, one workgroup per compute unit (the
+// large subsets).  256: 64-column panels and 128-row chunks in at most 80 KB
+// of LDS, so that two workgroups share a compute unit and one's diagonal
+// block latency overlaps the other's MFMA work (small subsets).
+template <typename T, int NTH>
+struct Shape {
+  static constexpr int NT = NTH;
+  static constexpr int NW = NTH / 64;
+  static constexpr int PB = NTH == 512 ? Cfg<T>::PB : 64;
   static constexpr int KC = Cfg<T>::KC;
+  static constexpr int RCH = NW * WR;         // chunk rows
   static constexpr int VW = 16 / sizeof(T);   // elements per 16-byte vector
   static constexpr int LDK = KC + VW;         // staged row stride (144 bytes)
   static constexpr int LDI = 64 + VW;         // inverse row stride
@@ -123,8 +130,11 @@ struct Smem {
   static constexpr int L21 = 64 * LDI * (int)sizeof(T);
   static constexpr int DG = 64 * LDD * 8;
   static constexpr int U0 = 2 * STAGE > DG ? 2 * STAGE : DG;  // two stage buffers
-  static constexpr int U = U0 > L21 ? U0 : L21;
+  static constexpr int U = NSUB == 2 && L21 > U0 ? L21 : U0;
 };
+// FP32 launches whose largest subset has npad up to this size use the
+// 256-thread shape (measured crossover: equal times at n = 1,500).
+constexpr int SMALL_NPAD = 1536;
 
 // In-register triangular solve on one 64-column sub-panel (accumulator block
 // rows B0..B0+3):  X^T = Inv * C^T, Inv lower triangular (LDS, row stride
@@ -134,7 +144,7 @@ template <typename T, int B0, int NBI, int NB>
 __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB], const T* Inv, int lr,
                                           int g) {
   typedef typename Cfg<T>::acc_t acc_t;
-  constexpr int LDI = Smem<T>::LDI;
+  constexpr int LDI = 64 + 16 / (int)sizeof(T);
 #pragma unroll
   for (int bo = 3; bo >= 0; --bo) {
     acc_t tmp[NB];
@@ -158,7 +168,8 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB]
 // followed by the inverse of the factor, stored transposed in the free upper
 // part: Inv[i][c] (i >= c) lives at Dg[c][i + 1].  Adds 2 sum log L_jj over
 // rows < nreal to ld and records the first failing pivot (1-based global
-// row) in bad (thread 0's copies).  All NT threads take part.
+// row) in bad (thread 0's copies).  All NW waves of the workgroup take part
+// (NW >= 4).
 //
 // Blocked in 16 x 16 tiles.  For each tile column kb:
 //   1. wave 0 factors the diagonal tile in registers, lane c holding column
@@ -177,6 +188,7 @@ __device__ __forceinline__ double rlane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+template <int NW>
 __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], double* rdiag, int nreal, int grow0,
                                    double& ld, int& bad) {
   typedef double f64x4_t __attribute__((ext_vector_type(4)));
@@ -271,9 +283,9 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
     {
       const int t = 3 - kb;
       const int npairs = t * (t + 1) / 2;
-      if (w < npairs) {
+      for (int pw = w; pw < npairs; pw += NW) {
         // pair index -> (I, K), K <= I, both in kb+1..3
-        int I = kb + 1, K = kb + 1, q = w;
+        int I = kb + 1, K = kb + 1, q = pw;
         while (q > I - (kb + 1)) {
           q -= I - kb;
           ++I;
@@ -329,8 +341,8 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
+template <typename T, int NTH>
+__global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order,
                                                  const ThetaDev* __restrict__ theta,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
@@ -338,7 +350,8 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
                                                  double* __restrict__ logdet,
                                                  int32_t* __restrict__ status) {
   typedef typename Cfg<T>::acc_t acc_t;
-  typedef Smem<T> SM;
+  typedef Shape<T, NTH> SM;
+  constexpr int NT = SM::NT, RCH = SM::RCH;
   constexpr int PB = SM::PB, KC = SM::KC, VW = SM::VW, LDK = SM::LDK, LDI = SM::LDI;
   constexpr int NBI = PB / 16;                    // accumulator block rows (panel columns)
   constexpr int NVEC = (PB + RCH) * (KC / VW);    // 16-byte vectors per stage
@@ -518,7 +531,7 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
         __syncthreads();
         if (tid < 64) Dg[tid][tid] = c0 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
         __syncthreads();
-        diag_factor_invert(Dg, Tb, rdiag, n - c0, c0, ld, bad);
+        diag_factor_invert<SM::NW>(Dg, Tb, rdiag, n - c0, c0, ld, bad);
         for (int e = tid; e < 64 * 64; e += NT) {
           const int i = e >> 6, j = e & 63;
           L[packed_rowoff32(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
@@ -588,7 +601,7 @@ __global__ __launch_bounds__(NT, 2) void k_potrf(const SubsetDesc* __restrict__ 
             __syncthreads();
             if (tid < 64) Dg[tid][tid] = c0 + 64 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
             __syncthreads();
-            diag_factor_invert(Dg, Tb, rdiag, n - c0 - 64, c0 + 64, ld, bad);
+            diag_factor_invert<SM::NW>(Dg, Tb, rdiag, n - c0 - 64, c0 + 64, ld, bad);
             for (int e = tid; e < 64 * 64; e += NT) {
               const int i = e >> 6, j = e & 63;
               L[packed_rowoff32(c0 + 64 + i) + c0 + 64 + j] = j <= i ? (T)Dg[i][j] : (T)0;
@@ -636,13 +649,18 @@ template <typename T>
 static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_items, const T* cx,
                                 const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(potrf::k_potrf<T>, dim3(n_items), dim3(potrf::NT), 0, Lc.stream, Lc.desc, order, Lc.theta,
+  hipLaunchKernelGGL((potrf::k_potrf<T, 512>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order, Lc.theta,
                      cx, cy, Lbuf, Inv, logdet, status);
   return hipGetLastError();
 }
-hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, const float* cx,
+hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
                             int32_t* status) {
+  if (n_items > 0 && max_npad <= potrf::SMALL_NPAD) {
+    hipLaunchKernelGGL((potrf::k_potrf<float, 256>), dim3(n_items), dim3(256), 0, L.stream, L.desc, order,
+                       L.theta, cx, cy, Lbuf, Inv, logdet, status);
+    return hipGetLastError();
+  }
   return potrf2_launch<float>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
 }
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
