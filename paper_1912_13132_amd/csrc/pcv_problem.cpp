@@ -546,8 +546,8 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
       for (int32_t c0 = 0; c0 < cnt; c0 += factor_chunk(p, cnt)) {
         const int32_t c = std::min(factor_chunk(p, cnt), cnt - c0);
         if (mixed)
-          HIPCHK(launch_potrf_f32(Lc, order + c0, c, p->max_npad, p->d_px32, p->d_py32, p->d_L32, p->d_Inv,
-                                  p->d_logdet, p->d_status));
+          HIPCHK(launch_potrf_f32(Lc, order + c0, c, p->desc[p->order_eval[G.o0 + c0]].npad, p->d_px32, p->d_py32,
+                                  p->d_L32, p->d_Inv, p->d_logdet, p->d_status));
         else
           HIPCHK(launch_potrf_f64(Lc, order + c0, c, p->d_px64, p->d_py64, p->d_L64, p->d_Inv, p->d_logdet,
                                   p->d_status));
@@ -982,8 +982,9 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
   if (mixed) {
     float* L = (float*)b.d_L;
     for (int32_t c0 = 0; c0 < pl.n_order; c0 += chunk) {
-      HIPCHK(launch_potrf_f32(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0), p->max_npad, p->d_px32,
-                              p->d_py32, L, b.d_Inv, b.d_logdet, b.d_status));
+      HIPCHK(launch_potrf_f32(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0),
+                              p->desc[p->order_eval[c0 / nb]].npad, p->d_px32, p->d_py32, L, b.d_Inv, b.d_logdet,
+                              b.d_status));
       HIPCHK(pace());
     }
     if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
