@@ -338,7 +338,11 @@ def main():
     src = os.path.join(ROOT, "paper_1912_13132_amd", "csrc", "pcv_potrf.hip")
     # FP32 launches whose largest subset has npad <= 1536 use 256-thread workgroups
     shape = 256 if a.prec == "mixed" and int(npad[act].max()) <= 1536 else 512
-    kname = f"k_potrf<{'float' if a.prec == 'mixed' else 'double'}, {shape}>"
+    # the third template argument: the launch shares its largest subsets
+    # between several workgroups
+    n_coop = int(rep["n_coop_subsets"])
+    kname = (f"k_potrf<{'float' if a.prec == 'mixed' else 'double'}, {shape}, {'true' if n_coop else 'false'}>"
+             + (f" ({n_coop} largest subsets shared by several workgroups)" if n_coop else ""))
     out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                        "frac": ach / peak,
                        "traffic": (measured_traffic(src, a.prec, n_first)

@@ -100,7 +100,18 @@ typedef struct {
                              so writes the caller queued there come first;
                              nothing is kept after the call returns.  The
                              other calls always take host arrays.  Default 0 */
-  int32_t reserved[4];
+  int32_t max_wg_per_subset; /* work-groups that may factor one subset together
+                             in pcv_eval's first factorisation launch: a subset
+                             whose padded size n is at least 2,048 and whose
+                             n^3 exceeds the launch's average n^3 per compute
+                             unit gets round(n^3 / average) of them, within
+                             [2, this], as long as the launch's shared
+                             work-groups fit one per compute unit.  Same
+                             factor bit for bit.  1 = one work-group per
+                             subset; 0 = default (8); at most 8.  Not used by
+                             a served problem or by the multi-theta launches
+                             of pcv_eval_batch */
+  int32_t reserved[3];
 } pcv_options;
 
 /* Per-evaluation report.  Arrays are optional, caller-owned, length S. */
@@ -135,9 +146,11 @@ typedef struct {
    * factorisation launch alone, ms_solve / ms_refine / ms_predict the first
    * group's later phases and ms_factor_all the factorisation of every subset
    * on its stream.  With one group n_factor_first = S evaluated subsets and
-   * ms_factor_all = ms_factor. */
+   * ms_factor_all = ms_factor.  n_coop_subsets of the first launch's
+   * largest subsets were each factored by several work-groups together
+   * (see max_wg_per_subset). */
   int32_t n_factor_first;
-  int32_t pad1;
+  int32_t n_coop_subsets;
   double ms_factor_all;
 } pcv_eval_report;
 

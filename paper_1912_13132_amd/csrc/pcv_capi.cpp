@@ -221,6 +221,8 @@ pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs, 
   if (o.prec != PCV_PREC_FP64 && o.prec != PCV_PREC_MIXED) return fail(PCV_ERR_INVALID, "opt.prec invalid");
   if (o.max_refine < 0 || o.max_refine > 8) return fail(PCV_ERR_INVALID, "opt.max_refine must be in [0, 8]");
   if (!(o.refine_tol >= 0.0)) return fail(PCV_ERR_INVALID, "opt.refine_tol must be >= 0");
+  if (o.max_wg_per_subset < 0 || o.max_wg_per_subset > 8)
+    return fail(PCV_ERR_INVALID, "opt.max_wg_per_subset must be in [0, 8]");
 
   pcv_problem* p = new pcv_problem();
   p->opt = o;

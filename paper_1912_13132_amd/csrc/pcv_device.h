@@ -15,6 +15,9 @@ constexpr int TB = 64;
 // Subset status codes: 0 = fine, k > 0 = pivot k-1 not positive,
 // PCV_STATUS_STAGNATED = mixed-precision refinement did not converge.
 constexpr int32_t PCV_STATUS_STAGNATED = -1;
+// PCV_STATUS_SYNC_TIMEOUT = a workgroup of a cooperative factorisation waited
+// past its bound for another (the factor is not usable; FP64 re-run).
+constexpr int32_t PCV_STATUS_SYNC_TIMEOUT = -2;
 
 // Per-subset descriptor.  Offsets are element offsets into the packed
 // device arrays.
@@ -72,14 +75,28 @@ struct Launch {
   const SubsetDesc* desc;
   const ThetaDev* theta;
 };
+// Cooperative factorisation: blocks 0 .. n_blocks - 1 of the launch share
+// subsets, info[b] = rank | nwg << 8 | slot << 16 (rank < nwg <= 255: the
+// block is rank `rank` of the nwg on subset order[b]; slot < n_slots picks
+// its 4 counters in sync, zeroed by the launcher).  The other blocks work
+// alone.  The ranks of a subset must be able to run at the same time: the
+// launcher's caller keeps the cooperative blocks first and at most one per
+// compute unit.
+struct CoopPlan {
+  const int32_t* info;
+  int n_blocks;
+  int32_t* sync;
+  int n_slots;
+};
 // max_npad: the largest padded size among the listed subsets (at most 1,536:
-// workgroups of 4 waves, two per compute unit; else 8 waves).
+// workgroups of 4 waves, two per compute unit; else 8 waves).  n_items counts
+// launch blocks (with cp, the cooperative blocks included).
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status);
+                            int32_t* status, const CoopPlan* cp = nullptr);
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
                             const double* cy, double* Lbuf, double* Inv, double* logdet,
-                            int32_t* status);
+                            int32_t* status, const CoopPlan* cp = nullptr);
 // max_npad: the largest padded size among the launched subsets (selects the
 // per-thread register budget of the solve kernels).
 hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,

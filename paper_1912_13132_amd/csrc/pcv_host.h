@@ -95,6 +95,16 @@ struct pcv_problem {
   hipStream_t post_stream[2] = {};
   std::vector<hipEvent_t> ev_fact;
   hipEvent_t ev_post[2] = {};
+  // The first factorisation launch of an evaluation (coop_group_cnt subsets
+  // of order_eval) with its largest subsets shared by several work-groups:
+  // coop_order lists the launch's blocks (coop_blocks shared ones first,
+  // then the other subsets alone), coop_info each shared block's rank, rank
+  // count and counter slot (coop_slots of them).  Empty when no subset is
+  // shared.
+  int32_t coop_group_cnt = 0;
+  int32_t coop_blocks = 0, coop_slots = 0;
+  std::vector<int32_t> coop_order, coop_info;
+  int32_t *d_coop_order = nullptr, *d_coop_info = nullptr, *d_coop_sync = nullptr;
 
   // device copies
   pcv::SubsetDesc* d_desc = nullptr;

@@ -29,6 +29,10 @@
 //   6. the finished rows are written to the packed tile-row factor.
 // The inverses of the diagonal blocks are also written (FP64) for the
 // triangular solves, and 2 sum log L_jj (FP64) for log det.
+// A cooperative launch (COOP) can give its largest subsets several 8-wave
+// workgroups each: the row chunks of every panel are dealt out among them,
+// with per-subset counters in device memory ordering the diagonal chunk
+// before the others' solves and each panel before the next one's update.
 #include <type_traits>
 
 #include "pcv_device.h"
@@ -341,14 +345,64 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
   }
 }
 
-template <typename T, int NTH>
+// ---- several workgroups on one subset
+// A cooperative launch gives a large subset several workgroups ("ranks"):
+// in every panel rank r takes the row chunks whose index within the panel is
+// r modulo the rank count, so rank 0 always holds the diagonal chunk.  Each
+// chunk's arithmetic is the same as with one workgroup, so the factor is the
+// same bit for bit.  Per subset, three counters in device memory (zeroed
+// before the launch): the panels whose diagonal chunk is stored (written by
+// rank 0), the rank-panels finished (every rank adds one per panel) and an
+// error word.  Waits are polled by thread 0 with a bounded count: a wait that
+// runs out marks the subset (status PCV_STATUS_SYNC_TIMEOUT) and the rank
+// carries on without waiting again, so every wave reaches the end.
+constexpr int COOP_SPIN = 1 << 21;  // polls, each about a microsecond or more
+
+// Thread 0 waits until *ctr >= target (agent-scope acquire); then the whole
+// workgroup continues with an acquire fence of its own.
+__device__ __forceinline__ void wg_wait(int32_t* ctr, int32_t target, int& tmo, int32_t* err) {
+  if (threadIdx.x == 0 && !tmo) {
+    int it = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++it > COOP_SPIN) {
+        tmo = 1;
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+// Every thread's earlier global stores are made visible at agent scope, then
+// thread 0 sets *ctr = value (set) or adds one (!set) with release order.
+__device__ __forceinline__ void wg_signal(int32_t* ctr, int32_t value, bool set) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (set)
+      __hip_atomic_store(ctr, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T, int NTH, bool COOP>
 __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order,
                                                  const ThetaDev* __restrict__ theta,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
                                                  T* __restrict__ Lbuf, double* __restrict__ Invbuf,
                                                  double* __restrict__ logdet,
-                                                 int32_t* __restrict__ status) {
+                                                 int32_t* __restrict__ status,
+                                                 const int32_t* __restrict__ coop_info, int n_coop,
+                                                 int32_t* __restrict__ coop_sync) {
   typedef typename Cfg<T>::acc_t acc_t;
   typedef Shape<T, NTH> SM;
   constexpr int NT = SM::NT, RCH = SM::RCH;
@@ -369,6 +423,21 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   T* L21s = reinterpret_cast<T*>(smem_u);  // [64][LDI]  -L21 (second half update)
   double(*Dg)[LDD] = reinterpret_cast<double(*)[LDD]>(smem_u);
 
+  // rank of this workgroup among the nwg that share the subset; blocks past
+  // the cooperative ones (and every block without COOP) work alone
+  int rank = 0, nwg = 1;
+  int32_t* sy = nullptr;
+  if constexpr (COOP) {
+    if ((int)blockIdx.x < n_coop) {
+      const int32_t info = coop_info[blockIdx.x];
+      rank = info & 255;
+      nwg = (info >> 8) & 255;
+      sy = coop_sync + 4 * (info >> 16);
+      if (nwg == 0) return;
+    }
+  }
+  int tmo = 0;  // thread 0: a wait ran out
+
   const int sidx = order[blockIdx.x];
   const SubsetDesc D = desc[sidx];
   const int n = D.n, npad = D.npad;
@@ -386,15 +455,20 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   double ld = 0.0;
   int bad = 0;
 
-  for (int c0 = 0; c0 < npad; c0 += PB) {
+  for (int c0 = 0, panel = 0; c0 < npad; c0 += PB, ++panel) {
     const bool two = (SM::NSUB == 2) && (c0 + 128 <= npad);
+    // cooperative ranks: the previous panel's rows are all stored (checked
+    // before the first update of this panel), this panel's diagonal inverse
+    // is in LDS (rank 0 makes it; the others read it once per panel)
+    bool synced = !COOP || nwg == 1 || c0 == 0;
+    bool inv_ready = !COOP || rank == 0;
     __syncthreads();  // previous panel done with colx / coly
     if (tid < PB) {
       const int col = min(c0 + tid, npad - 1);
       colx[tid] = X[col];
       coly[tid] = Y[col];
     }
-    for (int r0 = c0; r0 < npad; r0 += RCH) {
+    for (int r0 = c0 + RCH * rank; r0 < npad; r0 += RCH * nwg) {
       const bool first = (r0 == c0);
       const int wr0 = r0 + WR * w;          // this wave's first row
       const bool wact = wr0 < npad;
@@ -431,6 +505,13 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
           }
 #pragma unroll
           for (int bj = 0; bj < NBJ; ++bj) acc[bi][bj] = acc_t{tv[bj][0], tv[bj][1], tv[bj][2], tv[bj][3]};
+        }
+      }
+
+      if constexpr (COOP) {
+        if (!synced) {
+          wg_wait(sy + 1, nwg * panel, tmo, sy + 2);
+          synced = true;
         }
       }
 
@@ -513,6 +594,23 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
           if (k + 1 < nst) lstore(Ps + ((k + 1) & 1) * SBUF);
           if (k + 2 < nst) gload((k + 2) * KC);
           lds_barrier();
+        }
+      }
+
+      if constexpr (COOP) {
+        if (!inv_ready) {
+          // rank 0 has stored this panel's diagonal chunk (factor rows and
+          // the FP64 inverses): take the inverses as rank 0 holds them
+          wg_wait(sy, panel + 1, tmo, sy + 2);
+          for (int e = tid; e < 64 * 64; e += NT) {
+            const int i = e >> 6, j = e & 63;
+            InvS[0][i * LDI + j] = (T)Inv[(int64_t)(c0 / 64) * 4096 + e];
+            if constexpr (SM::NSUB == 2) {
+              if (two) InvS[1][i * LDI + j] = (T)Inv[(int64_t)(c0 / 64 + 1) * 4096 + e];
+            }
+          }
+          __syncthreads();
+          inv_ready = true;
         }
       }
 
@@ -635,6 +733,26 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
           }
         }
       }
+      if constexpr (COOP) {
+        if (first && nwg > 1) wg_signal(sy, panel + 1, true);  // diagonal chunk stored
+      }
+    }
+    if constexpr (COOP) {
+      // arrive once per panel, and only after the previous panel's arrivals
+      // are all in, so that a count of nwg * p means panels < p are done
+      if (nwg > 1) {
+        if (!synced) wg_wait(sy + 1, nwg * panel, tmo, sy + 2);
+        wg_signal(sy + 1, 0, false);
+      }
+    }
+  }
+  if constexpr (COOP) {
+    if (nwg > 1 && rank != 0) return;
+    if (nwg > 1) {
+      // every rank done: a wait that ran out anywhere is in the error word
+      wg_wait(sy + 1, nwg * ((npad + PB - 1) / PB), tmo, sy + 2);
+      if (tid == 0 && (tmo || __hip_atomic_load(sy + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)))
+        bad = PCV_STATUS_SYNC_TIMEOUT;
     }
   }
   if (tid == 0) {
@@ -647,26 +765,36 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
 
 template <typename T>
 static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_items, const T* cx,
-                                const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status) {
+                                const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status,
+                                const CoopPlan* cp) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL((potrf::k_potrf<T, 512>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order, Lc.theta,
-                     cx, cy, Lbuf, Inv, logdet, status);
+  if (cp && cp->n_blocks > 0) {
+    if (cp->n_blocks > n_items || cp->n_slots <= 0 || !cp->info || !cp->sync) return hipErrorInvalidValue;
+    const int nz = 4 * cp->n_slots;
+    hipLaunchKernelGGL(potrf::k_fill_i32, dim3((nz + 255) / 256), dim3(256), 0, Lc.stream, cp->sync, nz, 0);
+    hipLaunchKernelGGL((potrf::k_potrf<T, 512, true>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order,
+                       Lc.theta, cx, cy, Lbuf, Inv, logdet, status, cp->info, cp->n_blocks, cp->sync);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((potrf::k_potrf<T, 512, false>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order,
+                     Lc.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
   return hipGetLastError();
 }
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status) {
+                            int32_t* status, const CoopPlan* cp) {
   if (n_items > 0 && max_npad <= potrf::SMALL_NPAD) {
-    hipLaunchKernelGGL((potrf::k_potrf<float, 256>), dim3(n_items), dim3(256), 0, L.stream, L.desc, order,
-                       L.theta, cx, cy, Lbuf, Inv, logdet, status);
+    if (cp && cp->n_blocks > 0) return hipErrorInvalidValue;  // cooperative ranks use 8-wave workgroups
+    hipLaunchKernelGGL((potrf::k_potrf<float, 256, false>), dim3(n_items), dim3(256), 0, L.stream, L.desc, order,
+                       L.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
     return hipGetLastError();
   }
-  return potrf2_launch<float>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
+  return potrf2_launch<float>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status, cp);
 }
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
                             const double* cy, double* Lbuf, double* Inv, double* logdet,
-                            int32_t* status) {
-  return potrf2_launch<double>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status);
+                            int32_t* status, const CoopPlan* cp) {
+  return potrf2_launch<double>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status, cp);
 }
 
 }  // namespace pcv

@@ -90,6 +90,45 @@ std::vector<int32_t> lpt_order(const std::vector<SubsetDesc>& d, const std::vect
   return o;
 }
 
+// Work-groups per subset in the first factorisation launch.  With one
+// work-group per subset the launch lasts at least as long as its largest
+// factorisation; a subset whose cost (npad^3) exceeds the launch's average
+// cost per compute unit is shared by round(cost / average) work-groups (at
+// least 2, at most max_wg_per_subset), largest first, while the shared
+// blocks fit one per compute unit.  Sharing pays only with several 256-row
+// chunks per panel, hence the size floor.
+constexpr int32_t COOP_MIN_NPAD = 2048;
+void plan_coop(pcv_problem* p) {
+  const pcv_group& G0 = p->groups.empty() ? p->g_all : p->groups[0];
+  p->coop_group_cnt = G0.cnt;
+  const int maxwg = p->opt.max_wg_per_subset ? p->opt.max_wg_per_subset : 8;
+  if (maxwg < 2 || p->n_cu < 2 || G0.cnt <= 0) return;
+  double tot = 0.0;
+  for (int32_t k = 0; k < G0.cnt; ++k) tot += std::pow((double)p->desc[p->order_eval[G0.o0 + k]].npad, 3);
+  const double avg = tot / p->n_cu;
+  std::vector<int32_t> order, info;
+  int32_t used = 0, slots = 0, k = 0;
+  for (; k < G0.cnt; ++k) {
+    const int32_t i = p->order_eval[G0.o0 + k];
+    const double c = std::pow((double)p->desc[i].npad, 3);
+    if (p->desc[i].npad < COOP_MIN_NPAD || c <= avg) break;
+    const int32_t nwg = std::min<int32_t>(maxwg, std::max<int32_t>(2, (int32_t)std::lround(c / avg)));
+    if (used + nwg > p->n_cu) break;
+    for (int32_t r = 0; r < nwg; ++r) {
+      order.push_back(i);
+      info.push_back(r | nwg << 8 | slots << 16);
+    }
+    used += nwg;
+    ++slots;
+  }
+  if (slots == 0) return;
+  for (; k < G0.cnt; ++k) order.push_back(p->order_eval[G0.o0 + k]);
+  p->coop_blocks = used;
+  p->coop_slots = slots;
+  p->coop_order = std::move(order);
+  p->coop_info = std::move(info);
+}
+
 // Bucket grid over the core rectangles: G x G buckets spanning the domain,
 // each listing the cores that touch it.
 void build_router(pcv_problem* p) {
@@ -316,6 +355,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   p->g_all.cnt = p->n_active;
   p->g_all.nr = (int32_t)p->row_items_eval.size();
   p->g_all.nv = (int32_t)p->val_items.size();
+  plan_coop(p);
   // residual tiles: within each group, largest row block first
   p->tile_items = p->row_items_eval;
   for (const pcv_group& G : p->groups)
@@ -376,6 +416,11 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(upload(p, &p->d_desc, p->desc));
   TRY(upload(p, &p->d_order_eval, p->order_eval));
   TRY(upload(p, &p->d_order_all, p->order_all));
+  if (p->coop_slots > 0) {
+    TRY(upload(p, &p->d_coop_order, p->coop_order));
+    TRY(upload(p, &p->d_coop_info, p->coop_info));
+    TRY(dalloc(p, &p->d_coop_sync, (size_t)4 * p->coop_slots));
+  }
   TRY(upload(p, &p->d_active, p->active));
   TRY(upload(p, &p->d_row_items, p->row_items_eval));
   TRY(upload(p, &p->d_tile_items, p->tile_items));
@@ -543,6 +588,18 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
       HIPCHK(hipMemcpyAsync(p->d_theta, p->h_theta, sizeof(ThetaDev), hipMemcpyHostToDevice, st));
       break;
     case 1:
+      if (p->coop_slots > 0 && !p->served && G.o0 == 0 && cnt == p->coop_group_cnt) {
+        // the first launch with its largest subsets shared by several work-groups
+        const CoopPlan cp{p->d_coop_info, p->coop_blocks, p->d_coop_sync, p->coop_slots};
+        const int nb = (int)p->coop_order.size();
+        if (mixed)
+          HIPCHK(launch_potrf_f32(Lc, p->d_coop_order, nb, p->desc[p->order_eval[0]].npad, p->d_px32,
+                                  p->d_py32, p->d_L32, p->d_Inv, p->d_logdet, p->d_status, &cp));
+        else
+          HIPCHK(launch_potrf_f64(Lc, p->d_coop_order, nb, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
+                                  p->d_logdet, p->d_status, &cp));
+        break;
+      }
       for (int32_t c0 = 0; c0 < cnt; c0 += factor_chunk(p, cnt)) {
         const int32_t c = std::min(factor_chunk(p, cnt), cnt - c0);
         if (mixed)
@@ -759,6 +816,9 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     for (int32_t i : p->order_eval)
       if (status[i] || force_fb) bad.push_back(i);
     if (!mixed) {
+      if (status[bad[0]] == PCV_STATUS_SYNC_TIMEOUT)
+        return fail(PCV_ERR_DEVICE, "subset " + std::to_string(bad[0]) +
+                                        ": a work-group of its shared factorisation waited past its bound");
       return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(bad[0]) + " is not positive definite (pivot " +
                                       std::to_string(status[bad[0]] - 1) + ")");
     }
@@ -835,6 +895,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
     rep->ms_factor_all = 0.0;
     rep->n_factor_first = n_groups(p) > 1 ? p->groups[0].cnt : p->n_active;
+    rep->n_coop_subsets = p->served ? 0 : p->coop_slots;
     if (p->events) {
       float ms;
       HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
@@ -1040,6 +1101,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
     rep->ms_factor_all = 0.0;
     rep->n_factor_first = p->n_active;
+    rep->n_coop_subsets = 0;
     rep->n_fallback_fp64 = 0;
     rep->n_val = p->n_val_total;
     rep->n_subsets_used = p->n_active;
@@ -1066,6 +1128,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
         rep->ms_reduce += r1.ms_reduce;
         rep->ms_factor_all += r1.ms_factor_all;
         rep->n_factor_first = r1.n_factor_first;
+        rep->n_coop_subsets = r1.n_coop_subsets;
         rep->n_fallback_fp64 += r1.n_fallback_fp64;
       }
     }

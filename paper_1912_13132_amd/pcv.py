@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("refine_tol", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("profile", ctypes.c_int32),
                 ("debug_flags", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("inputs_on_device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("inputs_on_device", ctypes.c_int32), ("max_wg_per_subset", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class EvalReport(ctypes.Structure):
@@ -58,7 +59,7 @@ class EvalReport(ctypes.Structure):
                 ("per_subset_sspe", _c_double_p), ("per_subset_logdet", _c_double_p),
                 ("per_subset_iters", _c_int32_p), ("neg2loglik", ctypes.c_double),
                 ("per_subset_neg2loglik", _c_double_p), ("n_factor_first", ctypes.c_int32),
-                ("pad1", ctypes.c_int32), ("ms_factor_all", ctypes.c_double)]
+                ("n_coop_subsets", ctypes.c_int32), ("ms_factor_all", ctypes.c_double)]
 
 
 class ServerReport(ctypes.Structure):
@@ -83,6 +84,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1912_13132_amd.build.build()")
+    # torch's HIP runtime is loaded before the library's: once the library has
+    # initialised the device, torch can no longer initialise it in the same
+    # process, and device tensors (the inputs_on_device option) need torch
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     L.pcv_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -239,7 +247,7 @@ class Problem:
 
     def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
                  prec="mixed", max_refine=1, refine_tol=1e-4, stream=None, mem_cap=0,
-                 profile=False, debug_flags=0, graph=True):
+                 profile=False, debug_flags=0, graph=True, max_wg_per_subset=0):
         """Arrays are numpy-like (host) or, when locs is a torch tensor on the
         GPU, torch tensors on that device (the library's inputs_on_device
         option); predict then takes and returns device tensors too."""
@@ -274,6 +282,7 @@ class Problem:
         opt.debug_flags = int(debug_flags)
         opt.graph = 1 if graph else 0
         opt.inputs_on_device = 1 if self.on_device else 0
+        opt.max_wg_per_subset = int(max_wg_per_subset)
         self.prec = prec
         h = ctypes.c_void_p()
         _check(L.pcv_problem_create(
@@ -314,7 +323,7 @@ class Problem:
         rep.per_subset_neg2loglik = _ptr(nll, ctypes.c_double)
         _check(L.pcv_eval(self._handle(), ctypes.byref(th), ctypes.byref(loss), ctypes.byref(rep)))
         d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
-             if not k.startswith("per_subset") and k not in ("pad0", "pad1")}
+             if not k.startswith("per_subset") and k != "pad0"}
         d.update(per_subset_sspe=z, per_subset_logdet=ld, per_subset_iters=it,
                  per_subset_neg2loglik=nll)
         return loss.value, d
@@ -333,7 +342,7 @@ class Problem:
         _check(L.pcv_eval_batch_ex(self._handle(), len(thetas), arr, _ptr(out, ctypes.c_double),
                                    ctypes.byref(rep)))
         d = {k: getattr(rep, k) for k, _ in EvalReport._fields_
-             if not k.startswith("per_subset") and k not in ("pad0", "pad1")}
+             if not k.startswith("per_subset") and k != "pad0"}
         return out, d
 
     def eval_grid(self, thetas):

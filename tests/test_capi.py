@@ -46,7 +46,7 @@ def _create(locs, y, tp, ti, vp, vi, rect=None, **kw):
 
 @pytest.mark.parametrize("case", [
     "idx_out_of_range", "neg_idx", "ptr_decreasing", "ptr_not_zero", "nan_y", "inf_loc",
-    "too_large", "bad_prec_refine",
+    "too_large", "bad_prec_refine", "bad_max_wg",
 ])
 def test_invalid_arguments_rejected_before_device_work(case):
     locs, y = _tiny()
@@ -76,6 +76,8 @@ def test_invalid_arguments_rejected_before_device_work(case):
         vp, vi = [0, 0], []
     elif case == "bad_prec_refine":
         kw = dict(max_refine=99)
+    elif case == "bad_max_wg":
+        kw = dict(max_wg_per_subset=9)
     with pytest.raises(pcv.PcvError) as e:
         _create(locs, y, tp, ti, vp, vi, **kw)
     assert e.value.status == 1

@@ -1,0 +1,98 @@
+"""Large subsets factored by several work-groups together (the
+max_wg_per_subset option): the cooperative launch must give the same bits
+as one work-group per subset, in every replay, for both precisions, and
+match the FP64 oracle.
+
+Each shared subset's row chunks are dealt out over its work-groups, panel by
+panel; the chunk arithmetic is unchanged, so the comparison is exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_13132_amd import pcv
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-6}
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _synthetic(sizes_T, sizes_V, seed, spread=3.0):
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 900 + seed]))
+    locs, y, tl, vl = [], [], [], []
+    off = 0
+    for nt, nv in zip(sizes_T, sizes_V):
+        locs.append(r.uniform(0, spread, (nt + nv, 2)))
+        y.append(r.standard_normal(nt + nv))
+        tl.append(np.arange(off, off + nt))
+        vl.append(np.arange(off + nt, off + nt + nv))
+        off += nt + nv
+    return (np.concatenate(locs), np.concatenate(y), np.r_[0, np.cumsum(sizes_T)],
+            np.concatenate(tl).astype(np.int32), np.r_[0, np.cumsum(sizes_V)],
+            np.concatenate(vl).astype(np.int32))
+
+
+def _run(data, prec, max_wg, graph=True, reps=2):
+    th = pcv.theta(0.4, 0.1)
+    with pcv.Problem(*data, prec=prec, max_wg_per_subset=max_wg, graph=graph) as P:
+        out = [P.eval(th, report=True) for _ in range(reps)]
+    for loss, rep in out[1:]:  # the counters are cleared before every launch
+        assert loss == out[0][0]
+        np.testing.assert_array_equal(rep["per_subset_logdet"], out[0][1]["per_subset_logdet"])
+    return out[0]
+
+
+# sizes: padded 3,008 / 2,560 / 2,112 (shared), 960 and 320 (alone), a
+# ragged 1-point subset and one without validation points
+SIZES_T = [3000, 2500, 2100, 900, 300, 1, 2200]
+SIZES_V = [60, 50, 40, 30, 20, 3, 0]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_shared_factorisation_same_bits(prec):
+    data = _synthetic(SIZES_T, SIZES_V, 1)
+    say(f"[case] shared factorisation prec={prec} sizes={SIZES_T} max_wg=1")
+    loss1, rep1 = _run(data, prec, 1)
+    assert rep1["n_coop_subsets"] == 0
+    for max_wg, graph in ((2, True), (3, False), (8, True), (0, True)):
+        say(f"[case] shared factorisation prec={prec} max_wg={max_wg} graph={graph}")
+        loss, rep = _run(data, prec, max_wg, graph=graph)
+        # the three active subsets of at least 2,048 padded rows are shared
+        assert rep["n_coop_subsets"] == 3, rep["n_coop_subsets"]
+        assert loss == loss1
+        for k in ("per_subset_sspe", "per_subset_logdet", "per_subset_neg2loglik"):
+            np.testing.assert_array_equal(rep[k], rep1[k], err_msg=k)
+        assert rep["n_fallback_fp64"] == rep1["n_fallback_fp64"] == 0
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_shared_factorisation_matches_oracle(prec):
+    data = _synthetic(SIZES_T, SIZES_V, 2)
+    say(f"[case] shared factorisation vs oracle prec={prec}")
+    ref = oracle.cv_loss(*data, 0, 0.4, 0.1)
+    loss, rep = _run(data, prec, 8, reps=1)
+    assert rep["n_coop_subsets"] == 3
+    assert abs(loss - ref["sspe"]) <= TOL[prec] * abs(ref["sspe"])
+    np.testing.assert_allclose(rep["per_subset_sspe"], ref["per_subset_sspe"], rtol=100 * TOL[prec])
+    act = ref["per_subset_nval"] > 0
+    np.testing.assert_allclose(rep["per_subset_logdet"][act], ref["per_subset_logdet"][act],
+                               rtol=1e-9 if prec == "fp64" else 1e-4, atol=1e-8)
+
+
+def test_only_the_largest_are_shared():
+    """Many small subsets and two large ones: only the two are shared (the
+    small ones are below the size floor and the average load)."""
+    sizes_T = [2600, 2300] + [150] * 300
+    sizes_V = [40, 40] + [5] * 300
+    data = _synthetic(sizes_T, sizes_V, 3, spread=1.0)
+    say("[case] shared factorisation: 2 large + 300 small")
+    loss1, rep1 = _run(data, "mixed", 1, reps=1)
+    loss, rep = _run(data, "mixed", 0)
+    assert rep["n_coop_subsets"] == 2
+    assert loss == loss1
+    np.testing.assert_array_equal(rep["per_subset_sspe"], rep1["per_subset_sspe"])

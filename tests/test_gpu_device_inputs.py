@@ -111,3 +111,25 @@ def test_device_option_rejects_short_array(w_plain):
     ptrs = [short.data_ptr()] + [t.data_ptr() for t in ts[1:]]
     st, msg = _raw_create(w_plain, ptrs, n=n_claim)
     assert st == 1, msg
+
+
+def test_torch_usable_after_the_library():
+    """A process that evaluates through the library before it touches torch
+    can still use torch on the device (the binding loads torch's runtime
+    first).  Run in a child process, so that nothing of this process's
+    state decides the order."""
+    import os
+    import subprocess
+    code = ("from paper_1912_13132_amd import pcv, workloads as W\n"
+            "w = W.plain_fp64()\n"
+            "P = pcv.Problem.from_workload(w)\n"
+            "print('loss', P.eval(pcv.theta(0.1, 0.05)), flush=True)\n"
+            "P.close()\n"
+            "import torch\n"
+            "t = torch.arange(5, dtype=torch.float64, device='cuda:0')\n"
+            "print('torch', float(t.sum()), flush=True)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("[case] library first, then torch, in a child process")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "torch 10.0" in r.stdout, r.stdout
