@@ -128,8 +128,9 @@ struct Tile {
 // inverse of the diagonal block is staged in LDS, the block's unknowns are
 // formed from it, and every thread then subtracts their contribution from the
 // partial sums it owns (kept in registers):
-//   forward  L z = b:   thread owns rows r = tid + 512 i, streams the row
-//                       segment L[r, c0:c0+64] (256 bytes in FP32);
+//   forward  L z = b:   the rows below the block stream their segments
+//                       L[r, c0:c0+64] (256 bytes in FP32), one 16-byte
+//                       part per lane, summed across lanes (see below);
 //   backward L^T x = z: thread owns column quads q = tid + 512 i (columns
 //                       4q..4q+3), streams L[c0+k, 4q:4q+4] for the block's
 //                       64 rows (coalesced across threads).
@@ -159,6 +160,12 @@ __device__ __forceinline__ void stage_inv(double (*IL)[65], const double* __rest
   }
 }
 
+// Forward pass, rows below block J: LPR lanes cover one row's 64-column
+// segment of L with a 16-byte load each, so one load instruction of a wave
+// reads RPW whole segments (coalesced), and the segment's dot product with
+// z_J is summed over the LPR lanes by a fixed butterfly.  The partial sum
+// t_r of row r = RPP P + RPW w + g (pass P, wave w, lane group g) lives in
+// lane P mod LPR of that group, slot P / LPR.
 template <typename T, int MR>
 __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_trsv_fwd(const SubsetDesc* __restrict__ desc,
                                                      const int32_t* __restrict__ order,
@@ -170,6 +177,10 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
                                                      double* __restrict__ rhs2out) {
   typedef typename SVec<T>::type vec_t;
   constexpr int VW = SVec<T>::W;
+  constexpr int LPR = TB / VW;           // lanes per row segment: 16 (FP32), 32 (FP64)
+  constexpr int RPW = 64 / LPR;          // row segments per wave and load
+  constexpr int RPP = (SNT / 64) * RPW;  // rows per pass of the workgroup
+  static_assert(RPP * LPR == SNT, "one slot covers SNT rows");
   __shared__ double IL[64][65];
   __shared__ double tJ[64], zJ[64];
   __shared__ double b2s[SNT / 64];
@@ -179,12 +190,12 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
   const T* __restrict__ L = Lbuf + D.offL;
   const double* __restrict__ Inv = Invbuf + D.offInv;
   double* __restrict__ z = zbuf + D.offP;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane / LPR, l = lane % LPR;
   double t[MR];
   double b2 = 0.0;
 #pragma unroll
   for (int i = 0; i < MR; ++i) {
-    const int row = tid + SNT * i;
+    const int row = RPP * (i * LPR + l) + RPW * w + g;
     double b = 0.0;
     if (row < npad) b = rhs_pad ? rhs_pad[D.offP + row] : (row < n ? rhs_train[D.offT + row] : 0.0);
     t[i] = b;
@@ -195,7 +206,7 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
     stage_inv(IL, Inv + (int64_t)J * TB * TB, tid);
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
-      const int row = tid + SNT * i;
+      const int row = RPP * (i * LPR + l) + RPW * w + g;
       if (row >= c0 && row < c0 + TB) tJ[row - c0] = t[i];
     }
     __syncthreads();
@@ -206,28 +217,33 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
       z[c0 + tid] = s;
     }
     __syncthreads();
+    double zl[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) zl[u] = zJ[VW * l + u];
+    const int P0 = (c0 + TB) / RPP, P1 = npad / RPP;
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
-      const int row = tid + SNT * i;
-      if (row >= c0 + TB && row < npad) {
-        const vec_t* Lr = reinterpret_cast<const vec_t*>(L + packed_rowoff32(row) + c0);
-        double acc = 0.0;
-        // the 64-column segment in 128-byte parts (bounds the vectors in flight)
-        constexpr int NH = sizeof(T) == 8 ? 4 : 2;
+      const int pa = max(P0, i * LPR), pb = min(P1, (i + 1) * LPR);
+      // four passes per step, their loads issued together; a pass beyond pb
+      // reloads pass P's row and its sum is dropped
+#pragma unroll 1
+      for (int P = pa; P < pb; P += 4) {
+        vec_t v[4];
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          constexpr int NV = TB / VW / NH;
-          vec_t v[NV];
-#pragma unroll
-          for (int k = 0; k < NV; ++k) v[k] = Lr[h * NV + k];
-#pragma unroll
-          for (int k = 0; k < NV; ++k) {
-            const T* e = reinterpret_cast<const T*>(&v[k]);
-#pragma unroll
-            for (int u = 0; u < VW; ++u) acc += (double)e[u] * zJ[(h * NV + k) * VW + u];
-          }
+        for (int k = 0; k < 4; ++k) {
+          const int row = RPP * (P + k < pb ? P + k : P) + RPW * w + g;
+          v[k] = *reinterpret_cast<const vec_t*>(L + packed_rowoff32(row) + c0 + VW * l);
         }
-        t[i] -= acc;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const T* e = reinterpret_cast<const T*>(&v[k]);
+          double a = 0.0;
+#pragma unroll
+          for (int u = 0; u < VW; ++u) a += (double)e[u] * zl[u];
+#pragma unroll
+          for (int off = LPR / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+          if (P + k < pb && l == P + k - i * LPR) t[i] -= a;
+        }
       }
     }
     __syncthreads();
@@ -695,8 +711,13 @@ static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items
                              const double* Inv, const double* rt, const double* rp, double* z,
                              double* rhs2) {
   if (n_items <= 0) return hipSuccess;
+  // slots per thread = npad / 512 at most; the 32-slot variant (subsets above
+  // 8,192 padded rows) spills part of its registers
   if (max_npad <= 4096)
     hipLaunchKernelGGL((k_trsv_fwd<T, 8>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
+                       rt, rp, z, rhs2);
+  else if (max_npad <= 8192)
+    hipLaunchKernelGGL((k_trsv_fwd<T, 16>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
                        rt, rp, z, rhs2);
   else
     hipLaunchKernelGGL((k_trsv_fwd<T, 32>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,

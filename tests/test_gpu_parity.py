@@ -160,6 +160,23 @@ def test_subsets_above_4096_points(prec, tol):
                                rtol=1e-9 if prec == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_subset_above_8192_points(prec, tol):
+    """A subset of 9,000 training points: the solve variants for more than
+    8,192 padded rows (32 row slots per thread)."""
+    sizes_T = [9000, 200]
+    sizes_V = [90, 10]
+    locs, y, tp, ti, vp, vi = _synthetic(sizes_T, sizes_V, 6, spread=4.0)
+    say(f"[case] subset above 8192 prec={prec} sizes={sizes_T}")
+    ref = oracle.cv_loss(locs, y, tp, ti, vp, vi, 0, 0.4, 0.1)
+    with pcv.Problem(locs, y, tp, ti, vp, vi, prec=prec) as P:
+        loss, rep = P.eval(pcv.theta(0.4, 0.1), report=True)
+    assert _rel(loss, ref["sspe"]) <= tol
+    np.testing.assert_allclose(rep["per_subset_sspe"], ref["per_subset_sspe"], rtol=100 * tol)
+    np.testing.assert_allclose(rep["per_subset_logdet"], ref["per_subset_logdet"],
+                               rtol=1e-9 if prec == "fp64" else 1e-4)
+
+
 def test_no_nugget_fp64():
     """lambda = 0 is allowed (tau >= 0 in eq. (1)); distinct points keep M SPD."""
     locs, y, tp, ti, vp, vi = _synthetic([120, 90], [10, 10], 2)
