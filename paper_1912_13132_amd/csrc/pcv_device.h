@@ -88,12 +88,17 @@ struct CoopPlan {
   int32_t* sync;
   int n_slots;
 };
-// max_npad: the largest padded size among the listed subsets (at most 1,536:
-// workgroups of 4 waves, two per compute unit; else 8 waves).  n_items counts
-// launch blocks (with cp, the cooperative blocks included).
+// max_npad: the largest padded size among the listed subsets.  FP32 launches
+// with max_npad <= small_npad use workgroups of 4 waves (64-column panels,
+// two per compute unit), the others 8 waves; FACTOR_SMALL_NPAD is the
+// measured crossover for uniform sizes (equal times at n = 1,500).  n_items
+// counts launch blocks (with cp, the cooperative blocks included; cp needs
+// the 8-wave shape).
+constexpr int FACTOR_SMALL_NPAD = 1536;
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp = nullptr);
+                            int32_t* status, const CoopPlan* cp = nullptr,
+                            int small_npad = FACTOR_SMALL_NPAD);
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
                             const double* cy, double* Lbuf, double* Inv, double* logdet,
                             int32_t* status, const CoopPlan* cp = nullptr);

@@ -136,9 +136,6 @@ struct Shape {
   static constexpr int U0 = 2 * STAGE > DG ? 2 * STAGE : DG;  // two stage buffers
   static constexpr int U = NSUB == 2 && L21 > U0 ? L21 : U0;
 };
-// FP32 launches whose largest subset has npad up to this size use the
-// 256-thread shape (measured crossover: equal times at n = 1,500).
-constexpr int SMALL_NPAD = 1536;
 
 // In-register triangular solve on one 64-column sub-panel (accumulator block
 // rows B0..B0+3):  X^T = Inv * C^T, Inv lower triangular (LDS, row stride
@@ -782,8 +779,8 @@ static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_it
 }
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp) {
-  if (n_items > 0 && max_npad <= potrf::SMALL_NPAD) {
+                            int32_t* status, const CoopPlan* cp, int small_npad) {
+  if (n_items > 0 && max_npad <= small_npad) {
     if (cp && cp->n_blocks > 0) return hipErrorInvalidValue;  // cooperative ranks use 8-wave workgroups
     hipLaunchKernelGGL((potrf::k_potrf<float, 256, false>), dim3(n_items), dim3(256), 0, L.stream, L.desc, order,
                        L.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);

@@ -497,9 +497,8 @@ pcv_status ensure_post_streams(pcv_problem* p) {
 
 }  // namespace
 
-pcv_status set_served(pcv_problem* p, bool on) {
-  HIPCHK(hipSetDevice(p->device));
-  HIPCHK(hipStreamSynchronize(p->stream));
+// Drop the captured evaluations (they are captured again when next needed).
+void drop_graphs(pcv_problem* p) {
   if (p->graph_exec[0]) {
     (void)hipGraphExecDestroy(p->graph_exec[0]);
     p->graph_exec[0] = nullptr;
@@ -509,6 +508,12 @@ pcv_status set_served(pcv_problem* p, bool on) {
       (void)hipGraphExecDestroy(pl.graph);
       pl.graph = nullptr;
     }
+}
+
+pcv_status set_served(pcv_problem* p, bool on) {
+  HIPCHK(hipSetDevice(p->device));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  drop_graphs(p);
   drop_post_streams(p);
   p->served = on;
   return PCV_OK;
@@ -561,6 +566,13 @@ namespace {
 // of the first six.
 constexpr int N_PHASES = 7;
 
+// The first launch shares its largest subsets (planned, not served, and
+// that launch takes the 8-wave shape the sharing needs).
+bool coop_active(const pcv_problem* p) {
+  return p->coop_slots > 0 && !p->served && p->n_active > 0 &&
+         p->desc[p->order_eval[0]].npad > FACTOR_SMALL_NPAD;
+}
+
 // Subsets per factorisation launch: one launch, or for a served problem
 // launches of one work-group per compute unit.  A served problem's
 // evaluation runs launch by launch with the host waiting for each (the
@@ -588,7 +600,7 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
       HIPCHK(hipMemcpyAsync(p->d_theta, p->h_theta, sizeof(ThetaDev), hipMemcpyHostToDevice, st));
       break;
     case 1:
-      if (p->coop_slots > 0 && !p->served && G.o0 == 0 && cnt == p->coop_group_cnt) {
+      if (coop_active(p) && G.o0 == 0 && cnt == p->coop_group_cnt) {
         // the first launch with its largest subsets shared by several work-groups
         const CoopPlan cp{p->d_coop_info, p->coop_blocks, p->d_coop_sync, p->coop_slots};
         const int nb = (int)p->coop_order.size();
@@ -895,7 +907,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
     rep->ms_factor_all = 0.0;
     rep->n_factor_first = n_groups(p) > 1 ? p->groups[0].cnt : p->n_active;
-    rep->n_coop_subsets = p->served ? 0 : p->coop_slots;
+    rep->n_coop_subsets = coop_active(p) ? p->coop_slots : 0;
     if (p->events) {
       float ms;
       HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
