@@ -323,6 +323,10 @@ def main():
         "config": {"workload": descr,
                    "n_points": int(len(w.y)), "subsets": int(pt.n_subsets),
                    "train_min": int(nT.min()), "train_max": int(nT.max()),
+                   # evaluated subsets by training size (500-point buckets) and their total n^3
+                   "size_histogram": {f"{500 * k}-{500 * k + 499}": int(c) for k, c in
+                                      enumerate(np.bincount(nT[act] // 500)) if c},
+                   "sum_n3": float(np.sum(nT[act].astype(np.float64) ** 3)),
                    "n_val": int(rep["n_val"]), "theta_per_step": len(thetas),
                    "precision": a.prec, "max_refine": a.max_refine,
                    "launch": ("one launch per kernel for the step's theta values (batched), phase events "
