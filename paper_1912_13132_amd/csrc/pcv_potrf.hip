@@ -173,10 +173,10 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB]
 // (NW >= 4).
 //
 // Blocked in 16 x 16 tiles.  For each tile column kb:
-//   1. wave 0 factors the diagonal tile in registers, lane c holding column
-//      c of the (symmetric) tile: at pivot j the pivot and column j are
-//      broadcast with readlane and every lane updates its own column; then
-//      lane c builds column c of the tile's inverse by forward substitution;
+//   1. wave 0 factors the diagonal tile in registers, four entries per lane:
+//      at pivot j the pivot is broadcast with readlane and the column-j
+//      entries each lane needs come by lane shuffles; then lane c builds
+//      column c of the tile's inverse by forward substitution from LDS;
 //   2. the tiles below: X_I = A_Ik L_kk^{-T}, one FP64 MFMA tile per wave;
 //   3. the trailing lower block triangle: A_IK -= X_I X_K^T, one MFMA tile
 //      per wave.
@@ -198,12 +198,19 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
   for (int kb = 0; kb < 4; ++kb) {
     const int k0 = 16 * kb;
     // ---- leaf: factor and invert the diagonal tile in wave 0
-    // 1. diagonal tile, wave 0: lane l owns entries (r, c) = (l / 4, l % 4 + 4 u).
-    //    One wave touches LDS in program order, so no barrier is needed.
+    // 1. diagonal tile, wave 0: lane l holds entries (r, c) = (l / 4, l % 4 + 4 u)
+    //    of the tile in registers through the 16 pivot steps: the pivot by
+    //    readlane, A[r][j] from the lane's quad and A[c][j] from lane 4 c + j % 4
+    //    by lane shuffles; then the factored tile goes back to LDS.
     if (w == 0) {
-      const int r = l >> 2;
+      const int r = l >> 2, cq = l & 3;
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Dg[k0 + r][k0 + cq + 4 * u];
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double p = Dg[k0 + j][k0 + j];
+        const int uj = j >> 2, qj = j & 3;
+        double p = rlane(a[uj], 4 * j + qj);
         const bool ok = p > 0.0 && p < 1e300;
         if (!ok) p = 1.0;
         if (l == 0 && !ok && !bad) bad = grow0 + k0 + j + 1;
@@ -214,21 +221,21 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
         isp = isp * (1.5 - 0.5 * p * isp * isp);
         const double sp = p * isp, ip = isp * isp;
         if (l == 0) rdiag[k0 + j] = isp;
-        const double arj = Dg[k0 + r][k0 + j];
+        const double arj = __shfl(a[uj], (l & ~3) | qj, 64);
         const double arjp = arj * ip;
         double upd[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int c = (l & 3) + 4 * u;
-          upd[u] = Dg[k0 + r][k0 + c] - arjp * Dg[k0 + c][k0 + j];
-        }
+        for (int u = 0; u < 4; ++u) upd[u] = a[u] - arjp * __shfl(a[uj], 4 * (cq + 4 * u) + qj, 64);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int c = (l & 3) + 4 * u;
-          if (c == j && r >= j) Dg[k0 + r][k0 + j] = r == j ? sp : arj * isp;
-          if (c > j && r >= c) Dg[k0 + r][k0 + c] = upd[u];
+          const int c = cq + 4 * u;
+          if (c == j && r >= j) a[u] = r == j ? sp : arj * isp;
+          if (c > j && r >= c) a[u] = upd[u];
         }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (r >= cq + 4 * u) Dg[k0 + r][k0 + cq + 4 * u] = a[u];
     }
     __syncthreads();
     if (w == 0) {
