@@ -70,19 +70,32 @@ def copy_probe(torch, mib):
     return gbs
 
 
-def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=True, log=print):
+def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=True, log=print, warmup=0.0):
     """Kriging service on the factored problem: Poisson arrivals at `rate`
     requests/s for `seconds`, each with floor(10^U(0,4)) query locations
     uniform over the domain (gaps included), plus `n_opt` closed-loop
     optimisers each walking its own Latin-hypercube design of `n_lhs` points
-    over [theta/2, 2 theta] x [lambda/2, 2 lambda] through the same server."""
+    over [theta/2, 2 theta] x [lambda/2, 2 lambda] through the same server.
+    With warmup > 0 the same traffic first runs for `warmup` seconds on a
+    server that is then discarded (its latencies are not reported)."""
+    th0, lam0 = w.theta_true
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 5, seed]))
+    P = pcv.Problem.from_workload(w, prec="mixed")
+    P.factor(pcv.theta(th0, lam0, cov=w.cov))
+    if warmup > 0:
+        out = _serve_run(pcv, w, P, warmup, rate, n_opt, n_lhs, r, with_evals, seed)
+        log(f"[serve] warm-up ({warmup} s) done: p50 {out['p50_ms']:.1f} ms")
+    out = _serve_run(pcv, w, P, seconds, rate, n_opt, n_lhs, r, with_evals, seed)
+    P.close()
+    log(f"[serve] {'with' if with_evals else 'without'} evaluations: {out}")
+    return out
+
+
+def _serve_run(pcv, w, P, seconds, rate, n_opt, n_lhs, r, with_evals, seed):
     import threading
     import queue
     th0, lam0 = w.theta_true
-    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 5, seed]))
     lo, hi = w.locs.min(0), w.locs.max(0)
-    P = pcv.Problem.from_workload(w, prec="mixed")
-    P.factor(pcv.theta(th0, lam0, cov=w.cov))
     srv = pcv.Server(P, max_inflight=256)
     stop = threading.Event()
     evals = []
@@ -131,16 +144,13 @@ def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=Tr
         t.join()
     rep = srv.report()
     srv.close()
-    P.close()
-    out = {"requests": rep["n_predict"], "queries": rep["n_queries"],
+    return {"requests": rep["n_predict"], "queries": rep["n_queries"],
            "p50_ms": 1e3 * rep["p50_s"], "p99_ms": 1e3 * rep["p99_s"], "max_ms": 1e3 * rep["max_s"],
            "qps": rep["qps"], "evals": rep["n_eval"], "evals_per_s": rep["evals_per_s"],
            "eval_p50_ms": 1e3 * rep["eval_p50_s"], "eval_p99_ms": 1e3 * rep["eval_p99_s"],
            "batches": rep["n_batches"], "mean_batch_queries": rep["mean_batch_queries"],
            "admission_waits": rep["admission_waits"], "workspace_bytes": rep["workspace_bytes"],
            "seconds": seconds, "rate_req_per_s": rate, "optimisers": len(opts)}
-    log(f"[serve] {'with' if with_evals else 'without'} evaluations: {out}")
-    return out
 
 
 def _oracle_subset(args):
@@ -196,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--workload", default="large", choices=["large", "plain", "batched", "uneven"])
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 5M workload (testing)")
+    ap.add_argument("--serve-warmup", type=float, default=0.0,
+                    help="seconds of the same traffic on a discarded server before each serving run")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of each serving run (0 = skip serving)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -376,8 +388,8 @@ def main():
         out["speedup_vs_fp64_path"] = s64 / s_per
     if a.serve_seconds > 0 and a.workload == "large":
         out["serving"] = {
-            "with_4_optimisers": serve(pcv, w, a.serve_seconds, log=log),
-            "kriging_only": serve(pcv, w, a.serve_seconds, with_evals=False, log=log),
+            "with_4_optimisers": serve(pcv, w, a.serve_seconds, log=log, warmup=a.serve_warmup),
+            "kriging_only": serve(pcv, w, a.serve_seconds, with_evals=False, log=log, warmup=a.serve_warmup),
         }
     if not a.no_cpu:
         cb, rel = cpu_baseline(w, (thetas[0].range, thetas[0].lambda_), rep["per_subset_sspe"],
