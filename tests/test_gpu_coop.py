@@ -96,3 +96,25 @@ def test_only_the_largest_are_shared():
     assert rep["n_coop_subsets"] == 2
     assert loss == loss1
     np.testing.assert_array_equal(rep["per_subset_sspe"], rep1["per_subset_sspe"])
+
+
+def test_served_evaluation_same_bits_as_shared_launch():
+    """A problem held by a server evaluates launch by launch with one
+    work-group per subset (no shared launch); its losses carry the same bits
+    as pcv_eval with the largest subsets shared."""
+    data = _synthetic(SIZES_T, SIZES_V, 4)
+    th = [pcv.theta(0.4, 0.1), pcv.theta(0.3, 0.2)]
+    say("[case] served evaluation vs shared launch")
+    with pcv.Problem(*data, prec="mixed") as P:
+        direct = []
+        for t in th:
+            loss, rep = P.eval(t, report=True)
+            assert rep["n_coop_subsets"] == 3
+            direct.append(loss)
+        P.factor(th[0])
+        with pcv.Server(P) as srv:
+            losses = [srv.wait(srv.submit_eval(t)) for t in th]
+        # after the server: the shared launch again, same bits
+        after = P.eval(th[0], report=True)
+    assert losses == direct
+    assert after[0] == direct[0] and after[1]["n_coop_subsets"] == 3
