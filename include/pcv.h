@@ -110,7 +110,15 @@ typedef struct {
                              factor bit for bit.  1 = one work-group per
                              subset; 0 = default (8); at most 8.  Not used by
                              a served problem or by the multi-theta launches
-                             of pcv_eval_batch */
+                             of pcv_eval_batch.  The work-groups of a shared
+                             subset wait for each other with a bounded wait;
+                             two shared launches running at the same time on
+                             one device (problems evaluated concurrently on
+                             different streams) can hold each other's compute
+                             units until a wait runs out, and the subsets
+                             concerned are then re-run in FP64 (mixed) or the
+                             evaluation fails with PCV_ERR_DEVICE (FP64): set
+                             1 for problems evaluated concurrently */
   int32_t reserved[3];
 } pcv_options;
 
