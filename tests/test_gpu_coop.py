@@ -37,8 +37,8 @@ def _synthetic(sizes_T, sizes_V, seed, spread=3.0):
             np.concatenate(vl).astype(np.int32))
 
 
-def _run(data, prec, max_wg, graph=True, reps=2):
-    th = pcv.theta(0.4, 0.1)
+def _run(data, prec, max_wg, graph=True, reps=2, cov=0):
+    th = pcv.theta(0.4, 0.1, cov=cov)
     with pcv.Problem(*data, prec=prec, max_wg_per_subset=max_wg, graph=graph) as P:
         out = [P.eval(th, report=True) for _ in range(reps)]
     for loss, rep in out[1:]:  # the counters are cleared before every launch
@@ -71,11 +71,12 @@ def test_shared_factorisation_same_bits(prec):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_shared_factorisation_matches_oracle(prec):
+@pytest.mark.parametrize("cov", [pcv.COV_EXP, pcv.COV_MATERN32])
+def test_shared_factorisation_matches_oracle(prec, cov):
     data = _synthetic(SIZES_T, SIZES_V, 2)
-    say(f"[case] shared factorisation vs oracle prec={prec}")
-    ref = oracle.cv_loss(*data, 0, 0.4, 0.1)
-    loss, rep = _run(data, prec, 8, reps=1)
+    say(f"[case] shared factorisation vs oracle prec={prec} cov={cov}")
+    ref = oracle.cv_loss(*data, cov, 0.4, 0.1)
+    loss, rep = _run(data, prec, 8, reps=1, cov=cov)
     assert rep["n_coop_subsets"] == 3
     assert abs(loss - ref["sspe"]) <= TOL[prec] * abs(ref["sspe"])
     np.testing.assert_allclose(rep["per_subset_sspe"], ref["per_subset_sspe"], rtol=100 * TOL[prec])
