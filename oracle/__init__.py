@@ -23,4 +23,5 @@ from .pcv_oracle import (  # noqa: F401
     neg2_loglik_subset,
     gls_beta_subset,
 )
-from .mp_oracle import mp_subset_cv  # noqa: F401
+from .mp_oracle import mp_subset_cv, mp_predict  # noqa: F401
+from . import pcv_division as division  # noqa: F401

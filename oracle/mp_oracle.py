@@ -6,6 +6,13 @@ Sec. 3 from mpmath.exp / mpmath.sqrt, the inverse of Sigma + lambda I by
 mpmath's matrix inverse (no Cholesky), the prediction K^T M^{-1} y and the sum
 of squared errors.  Used to pin the float64 oracle on inputs where rounding is
 the only possible difference.
+
+The kriging variance (mp_predict) is computed a different way from the
+float64 oracle: as the conditional variance of a Gaussian vector, i.e. the
+reciprocal of the last diagonal entry of the precision matrix of the joint
+covariance of (y, Y(s_p)) under eq. (1), sigma^2 [[Sigma + lambda I, k],
+[k^T, 1]] (latent value) or with 1 + lambda in the corner (a new noisy
+observation).
 """
 import mpmath
 
@@ -50,3 +57,30 @@ def mp_subset_cv(locs_T, y_T, locs_V, y_V, kind, theta, lam, dps=50):
                 yhat.append(mpmath.fsum(_c(kind, _dist(T[a], v), th) * w[a] for a in range(n)))
         sspe = mpmath.fsum((yhat[j] - yV[j]) ** 2 for j in range(len(V)))
         return sspe, yhat
+
+
+def mp_predict(locs_T, y_T, q, kind, theta, lam, sigma2, obs_noise=False, dps=50):
+    """Kriging mean and variance at each query location, at `dps` digits,
+    from the joint Gaussian law of eq. (1): with C the covariance matrix of
+    (y_T, Y(q)) and P = C^{-1}, Var(Y(q) | y_T) = 1 / P[q, q] and
+    E(Y(q) | y_T) = -sum_a P[q, a] y_a / P[q, q].  Returns two lists."""
+    with mpmath.workdps(dps):
+        T = [(mpmath.mpf(float(p[0])), mpmath.mpf(float(p[1]))) for p in locs_T]
+        yT = [mpmath.mpf(float(v)) for v in y_T]
+        th = mpmath.mpf(float(theta))
+        lm = mpmath.mpf(float(lam))
+        s2 = mpmath.mpf(float(sigma2))
+        n = len(T)
+        means, vars_ = [], []
+        for p in q:
+            s = (mpmath.mpf(float(p[0])), mpmath.mpf(float(p[1])))
+            C = mpmath.matrix(n + 1, n + 1)
+            for a in range(n):
+                for b in range(n):
+                    C[a, b] = s2 * (_c(kind, _dist(T[a], T[b]), th) + (lm if a == b else 0))
+                C[a, n] = C[n, a] = s2 * _c(kind, _dist(T[a], s), th)
+            C[n, n] = s2 * (1 + (lm if obs_noise else 0))
+            Pm = C ** -1
+            vars_.append(1 / Pm[n, n])
+            means.append(-mpmath.fsum(Pm[n, a] * yT[a] for a in range(n)) / Pm[n, n])
+        return means, vars_

@@ -6,9 +6,7 @@ force at higher precision, or an invariant.  A dropped nugget, a sign error,
 a wrong index between training and validation points or a transposed operand
 fails at least one of them.
 """
-import json
 import math
-import os
 
 import mpmath
 import numpy as np
@@ -19,9 +17,6 @@ import scipy.stats as st
 
 import oracle
 from oracle import COV_EXP, COV_MATERN32
-
-HERE = os.path.dirname(os.path.abspath(__file__))
-
 
 def _rng(k):
     return np.random.default_rng(np.random.SeedSequence([1912, 13132, 900 + k]))
@@ -90,10 +85,12 @@ def _markov_1d(xs, ys, xp, th):
     return wa * ys[j - 1] + wb * ys[j], var
 
 
-def test_one_dimensional_screening():
+@pytest.mark.parametrize("sigma2", [1.0, 2.5])
+def test_one_dimensional_screening(sigma2):
     """Sec. 1 / Sec. 3.2 screening effect, exact for the 1-D exponential
-    model without nugget: closed-form neighbour weights and variance, and
-    points beyond the hull decay from the nearest observation."""
+    model without nugget: closed-form neighbour weights and variance (the
+    correlation-scale variance times sigma^2), and points beyond the hull
+    decay from the nearest observation."""
     r = _rng(4)
     xs = np.sort(r.uniform(0, 10, 40))
     ys = r.standard_normal(40)
@@ -101,11 +98,11 @@ def test_one_dimensional_screening():
     xp = np.concatenate([r.uniform(0, 10, 25), [-0.7, 11.3]])
     locT = np.c_[xs, np.zeros_like(xs)]
     locP = np.c_[xp, np.zeros_like(xp)]
-    mean, var = oracle.predict(locT, ys, locP, COV_EXP, th, 0.0, sigma2=1.0)
+    mean, var = oracle.predict(locT, ys, locP, COV_EXP, th, 0.0, sigma2=sigma2)
     for k, x in enumerate(xp):
         m, v = _markov_1d(xs, ys, x, th)
         assert mean[k] == pytest.approx(m, rel=1e-9, abs=1e-11)
-        assert var[k] == pytest.approx(v, rel=1e-8, abs=1e-10)
+        assert var[k] == pytest.approx(sigma2 * v, rel=1e-8, abs=1e-10)
     # removing points that are not neighbours of any query leaves yhat unchanged
     xq = np.array([3.3])
     j = np.searchsorted(xs, xq[0])
@@ -114,6 +111,58 @@ def test_one_dimensional_screening():
     m_all, _ = oracle.predict(locT, ys, np.c_[xq, [0.0]], COV_EXP, th, 0.0)
     m_sub, _ = oracle.predict(locT[keep], ys[keep], np.c_[xq, [0.0]], COV_EXP, th, 0.0)
     assert m_sub[0] == pytest.approx(m_all[0], rel=1e-10)
+
+
+# ------------------------------------------------------ kriging variance --
+@pytest.mark.parametrize("obs_noise", [False, True])
+@pytest.mark.parametrize("kind", [COV_EXP, COV_MATERN32])
+def test_predict_single_training_point_closed_form(kind, obs_noise):
+    """n = 1 with sigma^2 != 1 and lambda > 0: M = 1 + lambda, so the mean is
+    c(d) y1 / (1 + lambda) and the latent variance sigma^2 (1 - c(d)^2 /
+    (1 + lambda)); a new noisy observation adds tau = sigma^2 lambda.  A
+    dropped sigma^2, a nugget added as lambda instead of sigma^2 lambda or a
+    missing 1 + lambda in the denominator fails here."""
+    r = _rng(21)
+    sT = r.uniform(0, 1, (1, 2))
+    q = r.uniform(0, 1, (7, 2))
+    yT = r.standard_normal(1)
+    th, lam, s2 = 0.35, 0.3, 2.7
+    d = np.hypot(*(q - sT).T)
+    c = np.exp(-d / th) if kind == COV_EXP else (1 + d / th) * np.exp(-d / th)
+    mean, var = oracle.predict(sT, yT, q, kind, th, lam, sigma2=s2, obs_noise=obs_noise)
+    np.testing.assert_allclose(mean, c * yT[0] / (1.0 + lam), rtol=1e-14)
+    expect = s2 * (1.0 - c * c / (1.0 + lam)) + (s2 * lam if obs_noise else 0.0)
+    np.testing.assert_allclose(var, expect, rtol=1e-13)
+
+
+def test_predict_without_training_points_is_the_prior():
+    """No training data: the prior mean 0 and the prior variance sigma^2
+    (plus tau = sigma^2 lambda for a noisy observation)."""
+    q = np.array([[0.2, 0.4], [0.9, 0.1]])
+    m, v = oracle.predict(np.zeros((0, 2)), np.zeros(0), q, COV_EXP, 0.3, 0.2, sigma2=1.8)
+    np.testing.assert_array_equal(m, 0.0)
+    np.testing.assert_allclose(v, 1.8)
+    _, v = oracle.predict(np.zeros((0, 2)), np.zeros(0), q, COV_EXP, 0.3, 0.2, sigma2=1.8, obs_noise=True)
+    np.testing.assert_allclose(v, 1.8 * 1.2)
+
+
+@pytest.mark.parametrize("obs_noise", [False, True])
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_predict_against_gaussian_conditioning_50_digits(n, obs_noise):
+    """Mean and variance against a 50-digit evaluation through a different
+    identity: the conditional law of a Gaussian vector from the precision
+    matrix of the joint covariance of (y, Y(s_p)) under eq. (1), with
+    sigma^2 != 1 and a nugget."""
+    r = _rng(22 + n)
+    sT = r.uniform(0, 1, (n, 2))
+    yT = r.standard_normal(n)
+    q = r.uniform(0, 1, (4, 2))
+    kind = COV_EXP if n % 4 else COV_MATERN32
+    th, lam, s2 = 0.3, 0.15, 1.9
+    mean, var = oracle.predict(sT, yT, q, kind, th, lam, sigma2=s2, obs_noise=obs_noise)
+    mm, mv = oracle.mp_predict(sT, yT, q, kind, th, lam, s2, obs_noise=obs_noise)
+    np.testing.assert_allclose(mean, [float(v) for v in mm], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(var, [float(v) for v in mv], rtol=1e-12, atol=1e-14)
 
 
 # ---------------------------------------------------------------- P3 ------
@@ -351,18 +400,3 @@ def test_routing_half_open_rule():
     q = np.array([[0.5, 0.5], [1.0, 0.5], [2.0, 2.0], [1.0, 1.0], [0.0, 2.0],
                   [2.5, 0.2], [-1.0, -1.0], [1.5, 3.0]])
     np.testing.assert_array_equal(oracle.route_queries(q, R), [0, 1, 3, 3, 2, 1, 0, 3])
-
-
-# ------------------------------------------------------------- golden -----
-def test_paper_weak_scaling_subset_counts():
-    """Sec. 4.3.2: dividing 5,000,000 points into 512 subsets without shells
-    gives subsets of 9,765 or 9,766 points (printed in the paper)."""
-    from paper_1912_13132_amd import partition as part
-    with open(os.path.join(HERE, "golden", "weak_scaling_counts.json")) as f:
-        g = json.load(f)
-    r = _rng(18)
-    P = r.uniform(0, 1, (g["n_points"], 2)) * np.array([2.0, 1.0])
-    cores = part.recursive_cores(P, (0.0, 0.0, 2.0, 1.0), g["n_subsets"], 0.0)
-    owner = part.assign_cores(P, cores)
-    counts = np.bincount(owner, minlength=g["n_subsets"])
-    assert set(np.unique(counts).tolist()) <= set(g["allowed_counts"])
