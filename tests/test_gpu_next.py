@@ -1,10 +1,10 @@
 """GPU checks of the per-subset likelihood, the local-theta grid evaluation
 and the local-theta factorisation against the FP64 oracle.
 
-Tolerances: FP64 path 1e-10 relative on -2 log-likelihood per subset.  In
-mixed precision the log det comes from the FP32 factor: its relative error
-is bounded by ~n * 2^-24 per pivot in the worst case; the test allows 1e-5
-of |-2 l_i| and reports the largest difference seen.
+Tolerances: -2 log-likelihood per subset (eq. (2)) within the log det bound
+of tests/parity_util.py plus the loss tolerance (1e-10 FP64, 1e-6 mixed)
+relative to |-2 l_i| for the quadratic term; local losses per subset and
+theta within the loss tolerance.
 """
 import sys
 
@@ -14,6 +14,7 @@ import pytest
 import oracle
 from paper_1912_13132_amd import pcv
 from paper_1912_13132_amd import workloads as W
+from parity_util import TOL_SSPE, check_sspe, logdet_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -27,8 +28,8 @@ def w_small():
     return W.scaled("batched", 0.05)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
-def test_composite_likelihood_per_subset(w_small, prec, tol):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_composite_likelihood_per_subset(w_small, prec):
     pt = w_small.part
     th = pcv.theta(0.05, 0.1, sigma2=0.7)
     say(f"[case] likelihood prec={prec}")
@@ -41,10 +42,14 @@ def test_composite_likelihood_per_subset(w_small, prec, tol):
             continue
         T = pt.train_idx[pt.train_ptr[i]:pt.train_ptr[i + 1]]
         ref[i] = oracle.neg2_loglik_subset(w_small.locs[T], w_small.y[T], 0, 0.05, 0.1, 0.7)
-    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
-    say(f"   max rel diff {rel.max():.2e}")
-    assert rel.max() <= tol
-    assert abs(rep["neg2loglik"] - ref.sum()) <= tol * np.abs(ref).sum()
+    n = np.diff(pt.train_ptr)
+    act = np.diff(pt.val_ptr) > 0
+    bound = logdet_bound(prec, n, 0.1) + TOL_SSPE[prec] * np.abs(ref)
+    ratio = np.abs(got - ref)[act] / bound[act]
+    say(f"   max |diff| {np.abs(got - ref).max():.2e}, max diff / bound {ratio.max():.3f}")
+    assert ratio.max() <= 1.0
+    assert np.all(got[~act] == 0.0)
+    assert abs(rep["neg2loglik"] - ref.sum()) <= bound[act].sum()
 
 
 def test_local_best_theta_over_a_grid(w_small):
@@ -56,14 +61,15 @@ def test_local_best_theta_over_a_grid(w_small):
         losses, z, best = P.eval_grid(ths)
     zr = np.array([oracle.cv_loss(w_small.locs, w_small.y, pt.train_ptr, pt.train_idx, pt.val_ptr,
                                   pt.val_idx, 0, r_, l_)["per_subset_sspe"] for r_, l_ in g])
-    np.testing.assert_allclose(z, zr, rtol=1e-5, atol=1e-12)
+    for k in range(len(g)):
+        check_sspe(z[k], zr[k], "mixed", say, what=f"local SSPE at theta {k}")
     act = np.diff(pt.val_ptr) > 0
     assert np.all(best[~act] == -1)
     for i in np.nonzero(act)[0]:
         order = np.argsort(zr[:, i], kind="stable")
         k0, k1 = order[0], order[1]
         # where the two best differ by more than the tolerance the argmin is unique
-        if zr[k1, i] - zr[k0, i] > 1e-5 * zr[k0, i]:
+        if zr[k1, i] - zr[k0, i] > 2e-6 * zr[k0, i]:
             assert best[i] == k0
         else:
             assert best[i] in (k0, k1)

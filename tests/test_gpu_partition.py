@@ -1,12 +1,17 @@
-"""The device partitioner (pcv_part_*) against the host one: identical core
-rectangles, membership counts and subset lists (bit for bit), on seeded
-point sets with the workloads' structure, with and without shells, with the
-hold-out split and with the size cap."""
+"""The device partitioner (pcv_part_*) against the oracle's division written
+out from the definitions of Sec. 2.3 (shells) and Sec. 2.4 (recursive
+balanced division): identical core rectangles, membership counts and
+subset lists (bit for bit), on seeded point sets with the workloads'
+structure, with and without shells and with the hold-out split.  The
+oracle has no size cap (a sampling option of the workloads, not part of the
+division), so the capped case is checked against the host partitioner, whose
+uncapped output is itself pinned to the oracle on the CPU."""
 import sys
 
 import numpy as np
 import pytest
 
+from oracle import division as D
 from paper_1912_13132_amd import partition as part
 from paper_1912_13132_amd import pcv
 from paper_1912_13132_amd import workloads as W
@@ -33,6 +38,15 @@ def _points(kind, n, r):
     return P, (0.0, 0.0, 300.0, 400.0)
 
 
+def _same_as_oracle(pt, P, cores, delta):
+    owner, tp, ti, vp, vi = D.subsets(P, cores, delta, pt.is_val)
+    np.testing.assert_array_equal(pt.owner, owner)
+    np.testing.assert_array_equal(pt.train_ptr, tp)
+    np.testing.assert_array_equal(pt.train_idx, ti)
+    np.testing.assert_array_equal(pt.val_ptr, vp)
+    np.testing.assert_array_equal(pt.val_idx, vi)
+
+
 def _same_partition(a, b):
     np.testing.assert_array_equal(a.owner, b.owner)
     np.testing.assert_array_equal(a.is_val, b.is_val)
@@ -48,10 +62,10 @@ def test_recursive_division_matches_host(kind, m, delta):
     r = _rng({"uniform": 1, "thomas": 2, "lattice": 3}[kind] * 100 + m)
     P, dom = _points(kind, 60_000, r)
     say(f"[case] divide {kind} n={len(P)} m={m} delta={delta}")
-    host = part.recursive_cores(P, dom, m, delta)
+    ref = D.divide(P, dom, m, delta)
     dev = part.recursive_cores(P, dom, m, delta, device=True)
-    np.testing.assert_array_equal(dev, host)
-    assert part.count_memberships(P, host, delta, device=True) == part.count_memberships(P, host, delta)
+    np.testing.assert_array_equal(dev, ref)
+    assert part.count_memberships(P, ref, delta, device=True) == D.memberships(P, ref, delta)
 
 
 @pytest.mark.parametrize("kind,m,delta,cap", [("uniform", 30, 0.0, None), ("thomas", 64, 0.02, None),
@@ -59,10 +73,12 @@ def test_recursive_division_matches_host(kind, m, delta):
 def test_subsets_match_host(kind, m, delta, cap):
     r = _rng(7 + m)
     P, dom = _points(kind, 80_000, r)
-    cores = part.recursive_cores(P, dom, m, delta)
+    cores = D.divide(P, dom, m, delta)
     say(f"[case] subsets {kind} n={len(P)} m={m} delta={delta} cap={cap}")
-    a = part.build_partition(P, cores, delta, 0.1, _rng(99), cap=cap)
     b = part.build_partition(P, cores, delta, 0.1, _rng(99), cap=cap, device=True)
+    if cap is None:
+        _same_as_oracle(b, P, cores, delta)
+    a = part.build_partition(P, cores, delta, 0.1, _rng(99), cap=cap)
     _same_partition(a, b)
     assert a.info == b.info
 
@@ -70,12 +86,17 @@ def test_subsets_match_host(kind, m, delta, cap):
 def test_large_recipe_partition_matches_host():
     """The 5M-point workload's division (2,400 cores, 20% overlap), host vs
     device, end to end (delta search included)."""
-    say("[case] large partition host vs device")
+    say("[case] large partition host vs device, device vs oracle")
     h = W.large()
     d = W.large(device=True)
     np.testing.assert_array_equal(d.part.core_rect, h.part.core_rect)
     assert d.part.delta == h.part.delta
     _same_partition(d.part, h.part)
+    # the oracle's division at the delta the device search found
+    P = d.locs
+    dom = (0.0, 0.0, 2000.0, 2500.0)
+    np.testing.assert_array_equal(D.divide(P, dom, d.part.n_subsets, d.part.delta), d.part.core_rect)
+    _same_as_oracle(d.part, P, d.part.core_rect, d.part.delta)
 
 
 def test_partition_rejects_points_outside_the_cores():
