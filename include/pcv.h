@@ -87,7 +87,9 @@ typedef struct {
   int32_t profile;        /* nonzero: time each kernel phase with HIP events          */
   int32_t debug_flags;    /* testing hook, 0 in production.  Bit 0: in mixed mode
                              treat every FP32 factorisation as broken down, so the
-                             FP64 fallback path runs for every subset              */
+                             FP64 fallback path runs for every subset.  Bit 1:
+                             pcv_eval behaves as if another evaluation's shared
+                             launch held the device (see max_wg_per_subset)    */
   int32_t graph;          /* nonzero (default): capture the theta-evaluation once as a
                              HIP graph and replay it; 0: launch kernel by kernel  */
   int32_t inputs_on_device; /* nonzero: every array argument of pcv_problem_create
@@ -111,14 +113,20 @@ typedef struct {
                              subset; 0 = default (8); at most 8.  Not used by
                              a served problem or by the multi-theta launches
                              of pcv_eval_batch.  The work-groups of a shared
-                             subset wait for each other with a bounded wait;
-                             two shared launches running at the same time on
-                             one device (problems evaluated concurrently on
-                             different streams) can hold each other's compute
-                             units until a wait runs out, and the subsets
-                             concerned are then re-run in FP64 (mixed) or the
-                             evaluation fails with PCV_ERR_DEVICE (FP64): set
-                             1 for problems evaluated concurrently */
+                             subset wait for each other with a bounded wait,
+                             so at most one evaluation per device and process
+                             runs a shared launch at a time: an evaluation
+                             that finds one in flight on its device (another
+                             problem evaluated concurrently from another
+                             thread) factors with one work-group per subset,
+                             the same bits, and reports n_coop_subsets = 0.
+                             Shared launches of other processes on the same
+                             device are not seen; two of them side by side can
+                             hold each other's compute units until a wait runs
+                             out, and the subsets concerned are then re-run in
+                             FP64 (mixed) or the evaluation fails with
+                             PCV_ERR_DEVICE (FP64): set 1 when several
+                             processes evaluate on one device */
   int32_t reserved[3];
 } pcv_options;
 

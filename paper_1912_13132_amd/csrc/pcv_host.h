@@ -105,6 +105,7 @@ struct pcv_problem {
   int32_t coop_blocks = 0, coop_slots = 0;
   std::vector<int32_t> coop_order, coop_info;
   int32_t *d_coop_order = nullptr, *d_coop_info = nullptr, *d_coop_sync = nullptr;
+  bool coop_now = false;  // the current evaluation's first launch is shared
 
   // device copies
   pcv::SubsetDesc* d_desc = nullptr;
@@ -126,8 +127,9 @@ struct pcv_problem {
   double *d_logdet = nullptr, *d_sspe = nullptr, *d_quad = nullptr;
   int32_t* d_status = nullptr;
   int32_t* d_bad = nullptr;         // subsets re-run in FP64
-  // captured theta-evaluation: [0] whole, [1 + k] phase k (when profiling)
-  hipGraphExec_t graph_exec[8] = {};
+  // captured theta-evaluation: [0] as planned, [1] with one work-group per
+  // subset (used while another shared launch is in flight on the device)
+  hipGraphExec_t graph_exec[2] = {};
   pcv::ThetaDev* d_theta = nullptr;
   double* d_total = nullptr;
   int32_t* d_nbad = nullptr;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -484,14 +485,35 @@ void drop_post_streams(pcv_problem* p) {
   }
 }
 
+// The two post streams, their join events and one event per schedule group,
+// made together: created into locals and kept only when every creation
+// succeeded, so the problem holds either all of them or none.
 pcv_status ensure_post_streams(pcv_problem* p) {
-  if (p->post_stream[0]) return PCV_OK;
-  for (int q = 0; q < 2; ++q) {
-    HIPCHK(hipStreamCreateWithFlags(&p->post_stream[q], hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&p->ev_post[q], hipEventDisableTiming));
+  if (p->post_stream[0] && p->ev_fact.size() == p->groups.size()) return PCV_OK;
+  drop_post_streams(p);
+  hipStream_t st[2] = {};
+  hipEvent_t ep[2] = {};
+  std::vector<hipEvent_t> ef(p->groups.size(), nullptr);
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+    e = hipStreamCreateWithFlags(&st[q], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ep[q], hipEventDisableTiming);
   }
-  p->ev_fact.assign(p->groups.size(), nullptr);
-  for (auto& e : p->ev_fact) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (size_t k = 0; k < ef.size() && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ef[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    for (hipEvent_t x : ef)
+      if (x) (void)hipEventDestroy(x);
+    for (int q = 0; q < 2; ++q) {
+      if (ep[q]) (void)hipEventDestroy(ep[q]);
+      if (st[q]) (void)hipStreamDestroy(st[q]);
+    }
+    return fail(PCV_ERR_DEVICE, std::string("post streams: ") + hipGetErrorString(e));
+  }
+  for (int q = 0; q < 2; ++q) {
+    p->post_stream[q] = st[q];
+    p->ev_post[q] = ep[q];
+  }
+  p->ev_fact = std::move(ef);
   return PCV_OK;
 }
 
@@ -499,10 +521,11 @@ pcv_status ensure_post_streams(pcv_problem* p) {
 
 // Drop the captured evaluations (they are captured again when next needed).
 void drop_graphs(pcv_problem* p) {
-  if (p->graph_exec[0]) {
-    (void)hipGraphExecDestroy(p->graph_exec[0]);
-    p->graph_exec[0] = nullptr;
-  }
+  for (auto& g : p->graph_exec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
   for (auto& pl : p->batch.plans)
     if (pl.graph) {
       (void)hipGraphExecDestroy(pl.graph);
@@ -566,12 +589,42 @@ namespace {
 // of the first six.
 constexpr int N_PHASES = 7;
 
-// The first launch shares its largest subsets (planned, not served, and
+// The first launch may share its largest subsets (planned, not served, and
 // that launch takes the 8-wave shape the sharing needs).
 bool coop_active(const pcv_problem* p) {
   return p->coop_slots > 0 && !p->served && p->n_active > 0 &&
          p->desc[p->order_eval[0]].npad > FACTOR_SMALL_NPAD;
 }
+
+// At most one evaluation with a shared factorisation launch runs on a device
+// at a time in this process.  The work-groups of a shared subset wait for
+// each other, which is safe while every work-group of the launch can become
+// resident; two such launches side by side could hold each other's compute
+// units until their bounded waits run out.  An evaluation that finds its
+// device's flag taken factors with one work-group per subset instead (the
+// same bits).  The flag is released after the evaluation's stream has
+// drained.
+constexpr int COOP_MAX_DEVICES = 64;
+std::atomic<int> g_coop_busy[COOP_MAX_DEVICES];
+
+struct CoopGuard {
+  int dev = -1;
+  hipStream_t stream = nullptr;
+  bool held = false;
+  bool acquire(int d, hipStream_t st) {
+    if (d < 0 || d >= COOP_MAX_DEVICES) return false;
+    int z = 0;
+    held = g_coop_busy[d].compare_exchange_strong(z, 1, std::memory_order_acq_rel);
+    dev = d;
+    stream = st;
+    return held;
+  }
+  ~CoopGuard() {
+    if (!held) return;
+    (void)hipStreamSynchronize(stream);
+    g_coop_busy[dev].store(0, std::memory_order_release);
+  }
+};
 
 // Subsets per factorisation launch: one launch, or for a served problem
 // launches of one work-group per compute unit.  A served problem's
@@ -600,7 +653,7 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
       HIPCHK(hipMemcpyAsync(p->d_theta, p->h_theta, sizeof(ThetaDev), hipMemcpyHostToDevice, st));
       break;
     case 1:
-      if (coop_active(p) && G.o0 == 0 && cnt == p->coop_group_cnt) {
+      if (p->coop_now && G.o0 == 0 && cnt == p->coop_group_cnt) {
         // the first launch with its largest subsets shared by several work-groups
         const CoopPlan cp{p->d_coop_info, p->coop_blocks, p->d_coop_sync, p->coop_slots};
         const int nb = (int)p->coop_order.size();
@@ -687,6 +740,8 @@ pcv_status enqueue_all(pcv_problem* p, hipStream_t st, const hipStream_t* ps, bo
     for (int ph = 0; ph < N_PHASES && s == PCV_OK; ++ph) s = enqueue_phase(p, st, ph, mixed, sweeps, p->g_all);
     return s;
   }
+  if (p->ev_fact.size() != (size_t)K || !ps[0] || !ps[1])
+    return fail(PCV_ERR_STATE, "two-stream schedule without its streams and events");
   if ((s = enqueue_phase(p, st, 0, mixed, sweeps, p->g_all)) != PCV_OK) return s;
   for (int k = 0; k < K; ++k) {
     if ((s = enqueue_phase(p, st, 1, mixed, sweeps, p->groups[k])) != PCV_OK) return s;
@@ -753,6 +808,8 @@ pcv_status enqueue_profiled(pcv_problem* p, bool mixed, int sweeps) {
   hipStream_t st = p->stream;
   const int K = n_groups(p);
   const pcv_group& G0 = K > 1 ? p->groups[0] : p->g_all;
+  if (K > 1 && (p->ev_fact.size() != (size_t)K || !p->post_stream[0] || !p->post_stream[1]))
+    return fail(PCV_ERR_STATE, "two-stream schedule without its streams and events");
   pcv_status s = enqueue_phase(p, st, 0, mixed, sweeps, p->g_all);
   if (s != PCV_OK) return s;
   HIPCHK(hipEventRecord(p->ev[0], st));
@@ -796,11 +853,14 @@ pcv_status enqueue_eval(pcv_problem* p, bool mixed, int sweeps) {
   }
   if (p->events) return enqueue_profiled(p, mixed, sweeps);
   if (!p->opt.graph || p->served) return enqueue_all(p, p->stream, p->post_stream, mixed, sweeps);
-  if (!p->graph_exec[0]) {
-    pcv_status s = capture_eval(p, mixed, sweeps, &p->graph_exec[0]);
+  // [0]: the evaluation as planned; [1]: with one work-group per subset,
+  // for evaluations that find another shared launch in flight
+  hipGraphExec_t& g = (p->coop_now || !coop_active(p)) ? p->graph_exec[0] : p->graph_exec[1];
+  if (!g) {
+    pcv_status s = capture_eval(p, mixed, sweeps, &g);
     if (s != PCV_OK) return s;
   }
-  HIPCHK(hipGraphLaunch(p->graph_exec[0], p->stream));
+  HIPCHK(hipGraphLaunch(g, p->stream));
   return PCV_OK;
 }
 
@@ -814,6 +874,9 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   if (s != PCV_OK) return s;
   set_theta_host(p, th);
   const int sweeps = mixed ? p->opt.max_refine : 0;
+  CoopGuard coop;
+  // debug bit 1: behave as if another shared launch held the device
+  p->coop_now = coop_active(p) && !(p->opt.debug_flags & 2) && coop.acquire(p->device, p->stream);
   s = enqueue_eval(p, mixed, sweeps);
   if (s != PCV_OK) return s;
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -907,7 +970,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     rep->ms_factor = rep->ms_solve = rep->ms_refine = rep->ms_predict = rep->ms_reduce = 0.0;
     rep->ms_factor_all = 0.0;
     rep->n_factor_first = n_groups(p) > 1 ? p->groups[0].cnt : p->n_active;
-    rep->n_coop_subsets = coop_active(p) ? p->coop_slots : 0;
+    rep->n_coop_subsets = p->coop_now ? p->coop_slots : 0;
     if (p->events) {
       float ms;
       HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));

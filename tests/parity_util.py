@@ -56,7 +56,9 @@ def check_logdet(got, ref, n, lam, prec, say=None):
     ref = np.asarray(ref, dtype=np.float64)
     b = logdet_bound(prec, n, lam)
     d = np.abs(got - ref)
-    ratio = float((d / b).max()) if d.size else 0.0
+    pos = b > 0
+    assert np.all(d[~pos] == 0.0), "log det of an empty subset"
+    ratio = float((d[pos] / b[pos]).max()) if pos.any() else 0.0
     if say:
         say(f"   log det: max |diff| {float(d.max(initial=0.0)):.2e}, max diff / bound {ratio:.3f}")
     assert ratio <= 1.0, ("log det", ratio)

@@ -120,3 +120,62 @@ def test_served_evaluation_same_bits_as_shared_launch():
         after = P.eval(th[0], report=True)
     assert losses == direct
     assert after[0] == direct[0] and after[1]["n_coop_subsets"] == 3
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_shared_launch_busy_device_falls_back_to_one_workgroup(prec):
+    """An evaluation that finds another shared launch in flight on its device
+    (forced by debug bit 1) factors with one work-group per subset: the same
+    bits, n_coop_subsets = 0, in graph replays and eager launches; the next
+    evaluation without the flag shares again."""
+    data = _synthetic(SIZES_T, SIZES_V, 5)
+    th = pcv.theta(0.4, 0.1)
+    say(f"[case] shared launch with the device flag taken prec={prec}")
+    loss1, rep1 = _run(data, prec, 1)
+    for graph in (True, False):
+        with pcv.Problem(*data, prec=prec, debug_flags=2, graph=graph) as P:
+            out = [P.eval(th, report=True) for _ in range(2)]
+        for loss, rep in out:
+            assert rep["n_coop_subsets"] == 0
+            assert loss == loss1
+            np.testing.assert_array_equal(rep["per_subset_logdet"], rep1["per_subset_logdet"])
+    loss8, rep8 = _run(data, prec, 8)
+    assert rep8["n_coop_subsets"] == 3 and loss8 == loss1
+
+
+def test_concurrent_evaluations_from_two_threads():
+    """Two problems with shared launches evaluated at the same time from two
+    threads on their own streams: every result equals the one-work-group
+    factorisation bit for bit, and the shared launches never overlap (each
+    evaluation either shares or, while the other holds the device, does
+    not)."""
+    import threading
+    datas = [_synthetic(SIZES_T, SIZES_V, 6 + k) for k in range(2)]
+    th = pcv.theta(0.4, 0.1)
+    say("[case] two threads, two problems with shared launches")
+    ref = [_run(d, "mixed", 1, reps=1)[0] for d in datas]
+    probs = [pcv.Problem(*d, prec="mixed") for d in datas]
+    out = [[], []]
+    errs = []
+
+    def worker(k):
+        try:
+            for _ in range(6):
+                out[k].append(probs[k].eval(th, report=True))
+        except Exception as e:  # pragma: no cover - reported below
+            errs.append(e)
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for P in probs:
+        P.close()
+    assert not errs, errs
+    for k in range(2):
+        for loss, rep in out[k]:
+            assert loss == ref[k]
+            assert rep["n_coop_subsets"] in (0, 3)
+            assert rep["n_fallback_fp64"] == 0
+    say(f"   shared launches: {[sum(r['n_coop_subsets'] > 0 for _, r in o) for o in out]} of 6 each")
