@@ -255,6 +255,27 @@ pcv_status pcv_factor_local(pcv_problem* p, const pcv_theta* thetas);
 pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* mean,
                        double* var, int32_t obs_noise, int32_t* owner);
 
+/* For callers that cannot allocate device memory (code running beside a HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pcv_predict with every work buffer (grouped queries, work items, means,
+ * variances and the variance's per-item panels) in a fixed device array of
+ * PCV_NOALLOC_SCRATCH_MIB MiB inside the library, one per device, held from
+ * the first call on that device until the process ends.  The caller passes
+ * inputs and outputs as for pcv_predict (host arrays, or device arrays with
+ * inputs_on_device); results are bit for bit those of pcv_predict.  Calls no
+ * hipMalloc / hipFree; routing and the item plan on the host reuse buffers
+ * the problem keeps (grown by the first calls).  At most
+ * PCV_NOALLOC_MAX_QUERIES queries per call, else PCV_ERR_INVALID with
+ * nothing launched; items whose panels do not fit the array together run in
+ * consecutive launches.  Calls on one device share the array: the library
+ * serialises them inside a process (a per-device lock held until the call's
+ * stream has drained), and unsynchronised calls from outside that lock would
+ * race on it.  Errors as pcv_predict. */
+#define PCV_NOALLOC_SCRATCH_MIB 128
+#define PCV_NOALLOC_MAX_QUERIES 262144
+pcv_status pcv_predict_noalloc(pcv_problem* p, int64_t q, const double* qlocs, double* mean,
+                               double* var, int32_t obs_noise, int32_t* owner);
+
 /* Generalised least squares estimate of a linear mean in each subset (Sec. 5,
  * eq. (8)): beta_i = (X_i^T M_i^{-1} X_i)^{-1} X_i^T M_i^{-1} y_i through the
  * FP64 factors of the last pcv_factor / pcv_factor_local.

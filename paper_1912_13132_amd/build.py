@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libpcv.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HIP_SOURCES = ["pcv_potrf.hip", "pcv_kernels.hip", "pcv_krige.hip", "pcv_partition.hip"]
+HIP_SOURCES = ["pcv_potrf.hip", "pcv_kernels.hip", "pcv_krige.hip", "pcv_partition.hip", "pcv_noalloc.hip"]
 CPP_SOURCES = ["pcv_capi.cpp", "pcv_problem.cpp", "pcv_server.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -374,6 +374,31 @@ pcv_status pcv_predict(pcv_problem* p, int64_t q, const double* qlocs, double* m
   return pcv::predict_impl(p, q, qlocs, mean, var, obs_noise, owner, dev);
 }
 
+pcv_status pcv_predict_noalloc(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
+                               int32_t obs_noise, int32_t* owner) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  if (q < 0 || (q > 0 && (!qlocs || !mean))) return fail(PCV_ERR_INVALID, "bad query arguments");
+  if (q > PCV_NOALLOC_MAX_QUERIES)
+    return fail(PCV_ERR_INVALID, "pcv_predict_noalloc takes at most " + std::to_string(PCV_NOALLOC_MAX_QUERIES) +
+                                     " queries per call (got " + std::to_string(q) + ")");
+  const bool dev = p->opt.inputs_on_device != 0;
+  if (dev && q > 0) {
+    DeviceReader rd;
+    pcv_status st = check_device_range(mean, sizeof(double) * q, "mean");
+    if (st == PCV_OK && var) st = check_device_range(var, sizeof(double) * q, "var");
+    if (st == PCV_OK && owner) st = check_device_range(owner, sizeof(int32_t) * q, "owner");
+    if (st == PCV_OK) st = rd.begin(p->own_stream ? nullptr : (void*)p->stream);
+    if (st == PCV_OK) st = rd.read(p->na_q, qlocs, 2 * (size_t)q, "qlocs");
+    if (st != PCV_OK) return st;
+    qlocs = p->na_q.data();
+  }
+  for (int64_t j = 0; j < 2 * q; ++j)
+    if (!is_finite(qlocs[j])) return fail(PCV_ERR_INVALID, "non-finite query location");
+  if (!p->factored) return fail(PCV_ERR_STATE, "pcv_predict_noalloc called before pcv_factor");
+  return pcv::predict_noalloc_impl(p, q, qlocs, mean, var, obs_noise, owner, dev);
+}
+
 namespace {
 pcv_status check_points(int64_t n, const double* locs) {
   if (n < 1 || !locs) return fail(PCV_ERR_INVALID, "n must be >= 1 and locs non-NULL");

@@ -4,10 +4,24 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/pcv.h"
 #include "pcv_device.h"
+
+namespace pcv {
+// Host plan of one kriging launch: queries grouped by owning subset, in
+// 64-query items.  Input j of the plan is query j of the caller's list.
+struct KrigePlan {
+  std::vector<double> qx, qy;      // grouped, centred on the subset centroid
+  std::vector<int32_t> qorig;      // grouped -> input index
+  std::vector<int32_t> qflag;      // grouped flags (KRIGE_VAR | KRIGE_OBS_NOISE)
+  std::vector<KrigeItem> items;
+  int64_t w_doubles = 0;           // variance scratch
+  std::vector<int32_t> cnt, pos;   // counting-sort work arrays (size S)
+};
+}  // namespace pcv
 
 // Bucket grid over the core rectangles for routing query locations
 // (built once per problem when core rectangles are given).
@@ -162,6 +176,12 @@ struct pcv_problem {
   pcv_theta fact_theta{};
 
   pcv_batch batch;
+
+  // host buffers of pcv_predict_noalloc, reused from call to call
+  pcv::KrigePlan na_plan;
+  std::vector<int32_t> na_owner;
+  std::vector<std::pair<int32_t, int32_t>> na_groups;
+  std::vector<double> na_q;
 };
 
 namespace pcv {
@@ -182,6 +202,9 @@ pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta,
 pcv_status set_served(pcv_problem* p, bool on);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
                         int32_t obs_noise, int32_t* owner, bool dev_out = false);
+// predict_impl with every device buffer in the library's fixed scratch array
+pcv_status predict_noalloc_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
+                                int32_t obs_noise, int32_t* owner, bool dev_out);
 pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,
                          int32_t n_slots);
 pcv_status server_submit_predict(pcv_server* s, int64_t q, const double* ql, double* mean, double* var,
@@ -202,16 +225,6 @@ pcv_status part_subsets(int64_t n, const double* locs, int32_t S, const double* 
 // outside all of them; nearest training centroid without core rectangles).
 void route(const pcv_problem* p, int64_t q, const double* ql, int32_t* owner);
 
-// Host plan of one kriging launch: queries grouped by owning subset, in
-// 64-query items.  Input j of the plan is query j of the caller's list.
-struct KrigePlan {
-  std::vector<double> qx, qy;      // grouped, centred on the subset centroid
-  std::vector<int32_t> qorig;      // grouped -> input index
-  std::vector<int32_t> qflag;      // grouped flags (KRIGE_VAR | KRIGE_OBS_NOISE)
-  std::vector<KrigeItem> items;
-  int64_t w_doubles = 0;           // variance scratch
-  std::vector<int32_t> cnt, pos;   // counting-sort work arrays (size S)
-};
 // owner[j] is the subset of query j; flags[j] its flags (or `flag_all` when
 // flags is null).  Items get scratch only when they need the variance.
 void plan_krige(const pcv_problem* p, int64_t q, const double* ql, const int32_t* owner,

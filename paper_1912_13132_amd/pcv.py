@@ -109,6 +109,7 @@ def lib():
                                 _c_int32_p]
     L.pcv_predict.argtypes = [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
                               ctypes.c_int32, _c_int32_p]
+    L.pcv_predict_noalloc.argtypes = L.pcv_predict.argtypes
     L.pcv_problem_destroy.argtypes = [P]
     L.pcv_problem_info.argtypes = [P, _c_int32_p, _c_int64_p, _c_int32_p,
                                    ctypes.POINTER(ctypes.c_size_t)]
@@ -367,7 +368,11 @@ class Problem:
         arr = (Theta * self.S)(*thetas)
         _check(lib().pcv_factor_local(self._handle(), arr))
 
-    def predict(self, q, want_var=True, obs_noise=False):
+    def predict(self, q, want_var=True, obs_noise=False, noalloc=False):
+        """Kriging mean, variance (or None) and owning subset of every query;
+        noalloc=True goes through pcv_predict_noalloc (no device allocation,
+        at most 262,144 queries per call)."""
+        fn = lib().pcv_predict_noalloc if noalloc else lib().pcv_predict
         if self.on_device:
             import torch
             q = _dev(q, torch.float64, self._device).reshape(-1, 2)
@@ -375,7 +380,7 @@ class Problem:
             mean = torch.zeros(nq, dtype=torch.float64, device=self._device)
             var = torch.zeros(nq, dtype=torch.float64, device=self._device) if want_var else None
             owner = torch.zeros(nq, dtype=torch.int32, device=self._device)
-            _check(lib().pcv_predict(self._handle(), nq, _dptr(q, ctypes.c_double),
+            _check(fn(self._handle(), nq, _dptr(q, ctypes.c_double),
                                      _dptr(mean, ctypes.c_double),
                                      None if var is None else _dptr(var, ctypes.c_double),
                                      1 if obs_noise else 0, _dptr(owner, ctypes.c_int32)))
@@ -387,7 +392,7 @@ class Problem:
         mean = np.zeros(nq)
         var = np.zeros(nq) if want_var else None
         owner = np.zeros(nq, dtype=np.int32)
-        _check(lib().pcv_predict(self._handle(), nq, _ptr(q, ctypes.c_double),
+        _check(fn(self._handle(), nq, _ptr(q, ctypes.c_double),
                                  _ptr(mean, ctypes.c_double),
                                  None if var is None else _ptr(var, ctypes.c_double),
                                  1 if obs_noise else 0, _ptr(owner, ctypes.c_int32)))
