@@ -234,6 +234,49 @@ pcv_status pcv_eval_batch_ex(pcv_problem* p, int32_t n_theta, const pcv_theta* t
 pcv_status pcv_eval_grid(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,
                          double* per_subset_sspe, int32_t* best);
 
+/* Launch shapes and schedule picked by measurement.  pcv_autotune times
+ * pcv_eval at theta under the candidate choices that change a launch of this
+ * problem and keeps the fastest for every later evaluation of the problem
+ * (pcv_eval, pcv_eval_batch, served evaluations):
+ *   small_npad         FP32 factorisations whose schedule group's largest
+ *                      subset pads to at most this many rows use 4-wave
+ *                      work-groups with 64-column panels, the others 8-wave
+ *                      ones with 128-column panels (candidates 0, 1,024,
+ *                      1,536 = the default, 2,048, 3,072, 4,096; FP64 always
+ *                      uses 8-wave ones);
+ *   max_wg_per_subset  work-groups sharing one large subset in the first
+ *                      launch (1, 2, 3, 4, 6, 8; see pcv_options);
+ *   two_groups         1: the largest subsets in whole rounds of one
+ *                      work-group per compute unit, the rest in a second
+ *                      launch beside the first group's solves; 0: one launch.
+ * Coordinate search (small_npad, then max_wg_per_subset, then two_groups),
+ * candidates that launch the same shapes are timed once; each candidate is
+ * one warm-up evaluation (its graph is captured) and `reps` timed ones
+ * (median).  Sharing, the schedule groups and the graph change no bits; the
+ * shape threshold changes the factor's rounding (both shapes are within the
+ * mixed path's tolerance), so losses after tuning may differ from the
+ * defaults' in the last bits, and pcv_eval and pcv_eval_batch stay
+ * bit-identical to each other.
+ * cache_path (may be NULL): a text file of earlier choices, one line per
+ * problem shape, keyed by the device architecture, the HIP runtime version,
+ * this library's build, the precision and the padded sizes of the evaluated
+ * subsets in schedule order; a matching line is applied without timing
+ * (report->from_cache = 1), a new choice is appended.  reps in [1, 20].
+ * The problem must not be held by a server.  report may be NULL.
+ * Errors: PCV_ERR_INVALID (theta, reps), PCV_ERR_STATE (served),
+ * PCV_ERR_NOT_PD / PCV_ERR_DEVICE as pcv_eval. */
+typedef struct {
+  int32_t small_npad, max_wg_per_subset, two_groups;
+  int32_t from_cache;        /* 1: taken from the cache file, nothing timed     */
+  int32_t n_timed;           /* configurations timed                             */
+  int32_t pad0;
+  double default_s;          /* seconds per evaluation with the defaults         */
+  double best_s;             /* with the chosen configuration                    */
+  double tuning_s;           /* wall time of the call                            */
+} pcv_tune_report;
+pcv_status pcv_autotune(pcv_problem* p, const pcv_theta* theta, const char* cache_path, int32_t reps,
+                        pcv_tune_report* report);
+
 /* Factor every subset at theta in FP64 and keep L_i and
  * alpha_i = (Sigma_i + lambda I)^{-1} y_i resident for pcv_predict. */
 pcv_status pcv_factor(pcv_problem* p, const pcv_theta* theta);

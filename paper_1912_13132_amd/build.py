@@ -18,7 +18,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HIP_SOURCES = ["pcv_potrf.hip", "pcv_kernels.hip", "pcv_krige.hip", "pcv_partition.hip", "pcv_noalloc.hip"]
-CPP_SOURCES = ["pcv_capi.cpp", "pcv_problem.cpp", "pcv_server.cpp"]
+CPP_SOURCES = ["pcv_capi.cpp", "pcv_problem.cpp", "pcv_server.cpp", "pcv_tune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]

@@ -262,6 +262,16 @@ pcv_status pcv_eval(pcv_problem* p, const pcv_theta* theta, double* loss, pcv_ev
   return pcv::eval_impl(p, *theta, loss, report);
 }
 
+pcv_status pcv_autotune(pcv_problem* p, const pcv_theta* theta, const char* cache_path, int32_t reps,
+                        pcv_tune_report* report) {
+  pcv::g_err.clear();
+  if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");
+  pcv_status s = check_theta(theta);
+  if (s != PCV_OK) return s;
+  if (reps < 1 || reps > 20) return fail(PCV_ERR_INVALID, "reps must be in [1, 20]");
+  return pcv::autotune_impl(p, *theta, cache_path, reps, report);
+}
+
 pcv_status pcv_eval_batch(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses) {
   pcv::g_err.clear();
   if (!p) return fail(PCV_ERR_INVALID, "problem is NULL");

@@ -120,6 +120,12 @@ struct pcv_problem {
   std::vector<int32_t> coop_order, coop_info;
   int32_t *d_coop_order = nullptr, *d_coop_info = nullptr, *d_coop_sync = nullptr;
   bool coop_now = false;  // the current evaluation's first launch is shared
+  // Launch shapes and schedule (defaults, or the autotuner's choice): FP32
+  // factorisations whose schedule group's largest subset pads to at most
+  // tune_small_npad rows use 4-wave work-groups; tune_two_groups turns the
+  // two-group schedule on; opt.max_wg_per_subset bounds the sharing.
+  int32_t tune_small_npad = pcv::FACTOR_SMALL_NPAD;
+  bool tune_two_groups = true;
 
   // device copies
   pcv::SubsetDesc* d_desc = nullptr;
@@ -200,6 +206,13 @@ pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta,
 // Single-stream evaluation schedule while a server holds the problem (on)
 // or the two-stream schedule again (off); drops the captured evaluation.
 pcv_status set_served(pcv_problem* p, bool on);
+// Sharing plan of the first factorisation launch (coop_* fields) for the
+// current schedule groups and max_wg_per_subset; host side only.
+void plan_coop(pcv_problem* p);
+// Launch shapes and schedule of later evaluations (drops the captured ones).
+pcv_status apply_tuning(pcv_problem* p, int32_t small_npad, int32_t max_wg, bool two_groups);
+pcv_status autotune_impl(pcv_problem* p, const pcv_theta& th, const char* cache_path, int32_t reps,
+                         pcv_tune_report* rep);
 pcv_status predict_impl(pcv_problem* p, int64_t q, const double* qlocs, double* mean, double* var,
                         int32_t obs_noise, int32_t* owner, bool dev_out = false);
 // predict_impl with every device buffer in the library's fixed scratch array

@@ -91,6 +91,21 @@ std::vector<int32_t> lpt_order(const std::vector<SubsetDesc>& d, const std::vect
   return o;
 }
 
+// The schedule groups of an evaluation: whole rounds of one work-group per
+// compute unit over the largest subsets, then the remainder (when the
+// two-group schedule is on and applies), else one group.  A subset is
+// factored with the shape its group's largest subset selects, whatever
+// launches the group is split into, so its factor carries the same bits in
+// pcv_eval, in a served evaluation and in the multi-theta launches.
+int n_sched(const pcv_problem* p) {
+  return p->tune_two_groups && p->groups.size() > 1 ? (int)p->groups.size() : 1;
+}
+const pcv_group& sched(const pcv_problem* p, int k) { return n_sched(p) > 1 ? p->groups[k] : p->g_all; }
+int32_t sched_npad(const pcv_problem* p, int k) {
+  const pcv_group& G = sched(p, k);
+  return G.cnt > 0 ? p->desc[p->order_eval[G.o0]].npad : 0;
+}
+
 // Work-groups per subset in the first factorisation launch.  With one
 // work-group per subset the launch lasts at least as long as its largest
 // factorisation; a subset whose cost (npad^3) exceeds the launch's average
@@ -99,9 +114,15 @@ std::vector<int32_t> lpt_order(const std::vector<SubsetDesc>& d, const std::vect
 // blocks fit one per compute unit.  Sharing pays only with several 256-row
 // chunks per panel, hence the size floor.
 constexpr int32_t COOP_MIN_NPAD = 2048;
+
+}  // namespace
+
 void plan_coop(pcv_problem* p) {
-  const pcv_group& G0 = p->groups.empty() ? p->g_all : p->groups[0];
+  const pcv_group& G0 = sched(p, 0);
   p->coop_group_cnt = G0.cnt;
+  p->coop_blocks = p->coop_slots = 0;
+  p->coop_order.clear();
+  p->coop_info.clear();
   const int maxwg = p->opt.max_wg_per_subset ? p->opt.max_wg_per_subset : 8;
   if (maxwg < 2 || p->n_cu < 2 || G0.cnt <= 0) return;
   double tot = 0.0;
@@ -129,6 +150,8 @@ void plan_coop(pcv_problem* p) {
   p->coop_order = std::move(order);
   p->coop_info = std::move(info);
 }
+
+namespace {
 
 // Bucket grid over the core rectangles: G x G buckets spanning the domain,
 // each listing the cores that touch it.
@@ -261,6 +284,23 @@ void plan_krige(const pcv_problem* p, int64_t q, const double* ql, const int32_t
       P.items.push_back(it);
     }
 }
+
+namespace {
+// Device copies of the sharing plan (its blocks, their ranks and counters).
+pcv_status upload_coop(pcv_problem* p) {
+  if (p->coop_slots <= 0) return PCV_OK;
+  pcv_status s = upload(p, &p->d_coop_order, p->coop_order);
+  if (s == PCV_OK) s = upload(p, &p->d_coop_info, p->coop_info);
+  if (s == PCV_OK) s = dalloc(p, &p->d_coop_sync, (size_t)4 * p->coop_slots);
+  return s;
+}
+void free_coop(pcv_problem* p) {
+  dfree(p, p->d_coop_order, sizeof(int32_t) * std::max<size_t>(1, p->coop_order.size()));
+  dfree(p, p->d_coop_info, sizeof(int32_t) * std::max<size_t>(1, p->coop_info.size()));
+  dfree(p, p->d_coop_sync, sizeof(int32_t) * std::max<size_t>(1, (size_t)4 * p->coop_slots));
+  p->d_coop_order = p->d_coop_info = p->d_coop_sync = nullptr;
+}
+}  // namespace
 
 pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const double* y, int32_t S,
                          const int64_t* tptr, const int32_t* tidx, const int64_t* vptr,
@@ -417,11 +457,7 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(upload(p, &p->d_desc, p->desc));
   TRY(upload(p, &p->d_order_eval, p->order_eval));
   TRY(upload(p, &p->d_order_all, p->order_all));
-  if (p->coop_slots > 0) {
-    TRY(upload(p, &p->d_coop_order, p->coop_order));
-    TRY(upload(p, &p->d_coop_info, p->coop_info));
-    TRY(dalloc(p, &p->d_coop_sync, (size_t)4 * p->coop_slots));
-  }
+  TRY(upload_coop(p));
   TRY(upload(p, &p->d_active, p->active));
   TRY(upload(p, &p->d_row_items, p->row_items_eval));
   TRY(upload(p, &p->d_tile_items, p->tile_items));
@@ -542,6 +578,28 @@ pcv_status set_served(pcv_problem* p, bool on) {
   return PCV_OK;
 }
 
+pcv_status apply_tuning(pcv_problem* p, int32_t small_npad, int32_t max_wg, bool two_groups) {
+  if (max_wg < 0 || max_wg > 8 || small_npad < 0) return fail(PCV_ERR_INVALID, "bad tuning parameters");
+  HIPCHK(hipSetDevice(p->device));
+  HIPCHK(hipStreamSynchronize(p->stream));  // nothing in flight uses the old plan
+  drop_graphs(p);
+  drop_post_streams(p);
+  p->tune_small_npad = small_npad;
+  p->tune_two_groups = two_groups;
+  p->opt.max_wg_per_subset = max_wg;
+  free_coop(p);
+  plan_coop(p);
+  pcv_status s = upload_coop(p);
+  if (s != PCV_OK) {
+    // keep the problem usable: no sharing
+    free_coop(p);
+    p->coop_blocks = p->coop_slots = 0;
+    p->coop_order.clear();
+    p->coop_info.clear();
+  }
+  return s;
+}
+
 void problem_free(pcv_problem* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
@@ -590,10 +648,10 @@ namespace {
 constexpr int N_PHASES = 7;
 
 // The first launch may share its largest subsets (planned, not served, and
-// that launch takes the 8-wave shape the sharing needs).
+// in FP32 that launch takes the 8-wave shape the sharing needs).
 bool coop_active(const pcv_problem* p) {
   return p->coop_slots > 0 && !p->served && p->n_active > 0 &&
-         p->desc[p->order_eval[0]].npad > FACTOR_SMALL_NPAD;
+         (p->opt.prec != PCV_PREC_MIXED || sched_npad(p, 0) > p->tune_small_npad);
 }
 
 // At most one evaluation with a shared factorisation launch runs on a device
@@ -665,15 +723,21 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
                                   p->d_logdet, p->d_status, &cp));
         break;
       }
-      for (int32_t c0 = 0; c0 < cnt; c0 += factor_chunk(p, cnt)) {
-        const int32_t c = std::min(factor_chunk(p, cnt), cnt - c0);
-        if (mixed)
-          HIPCHK(launch_potrf_f32(Lc, order + c0, c, p->desc[p->order_eval[G.o0 + c0]].npad, p->d_px32, p->d_py32,
-                                  p->d_L32, p->d_Inv, p->d_logdet, p->d_status));
-        else
-          HIPCHK(launch_potrf_f64(Lc, order + c0, c, p->d_px64, p->d_py64, p->d_L64, p->d_Inv, p->d_logdet,
-                                  p->d_status));
-        PACE();
+      // the part of each schedule group inside G, in launches of
+      // factor_chunk subsets, each with its schedule group's shape
+      for (int k = 0; k < n_sched(p); ++k) {
+        const pcv_group& SG = sched(p, k);
+        const int32_t a = std::max(G.o0, SG.o0), e = std::min(G.o0 + cnt, SG.o0 + SG.cnt);
+        for (int32_t c0 = a; c0 < e; c0 += factor_chunk(p, e - a)) {
+          const int32_t c = std::min(factor_chunk(p, e - a), e - c0);
+          if (mixed)
+            HIPCHK(launch_potrf_f32(Lc, p->d_order_eval + c0, c, sched_npad(p, k), p->d_px32, p->d_py32, p->d_L32,
+                                    p->d_Inv, p->d_logdet, p->d_status, nullptr, p->tune_small_npad));
+          else
+            HIPCHK(launch_potrf_f64(Lc, p->d_order_eval + c0, c, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
+                                    p->d_logdet, p->d_status));
+          PACE();
+        }
       }
       break;
     case 2:
@@ -731,7 +795,7 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
 // factorisations run group after group on st and each group's later phases
 // on post stream k % 2 once its factorisation is done; the post streams are
 // joined back into st before the reduction.
-int n_groups(const pcv_problem* p) { return p->served ? 1 : (int)p->groups.size(); }
+int n_groups(const pcv_problem* p) { return p->served ? 1 : n_sched(p); }
 
 pcv_status enqueue_all(pcv_problem* p, hipStream_t st, const hipStream_t* ps, bool mixed, int sweeps) {
   pcv_status s = PCV_OK;
@@ -1117,11 +1181,17 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
   if (ev) HIPCHK(hipEventRecord(p->ev[0], st));
   if (mixed) {
     float* L = (float*)b.d_L;
-    for (int32_t c0 = 0; c0 < pl.n_order; c0 += chunk) {
-      HIPCHK(launch_potrf_f32(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0),
-                              p->desc[p->order_eval[c0 / nb]].npad, p->d_px32, p->d_py32, L, b.d_Inv, b.d_logdet,
-                              b.d_status));
-      HIPCHK(pace());
+    // pairs are ordered subset by subset (LPT), nb theta slots each: the
+    // pairs of each schedule group take that group's shape, as in pcv_eval
+    for (int k = 0; k < n_sched(p); ++k) {
+      const pcv_group& SG = sched(p, k);
+      const int32_t a = SG.o0 * nb, e = std::min(pl.n_order, (SG.o0 + SG.cnt) * nb);
+      const int32_t ck = factor_chunk(p, e - a);
+      for (int32_t c0 = a; c0 < e; c0 += ck) {
+        HIPCHK(launch_potrf_f32(Lc, pl.d_order + c0, std::min(ck, e - c0), sched_npad(p, k), p->d_px32, p->d_py32,
+                                L, b.d_Inv, b.d_logdet, b.d_status, nullptr, p->tune_small_npad));
+        HIPCHK(pace());
+      }
     }
     if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
     HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));

@@ -39,6 +39,13 @@ class Theta(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("sigma2", ctypes.c_double)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("small_npad", ctypes.c_int32), ("max_wg_per_subset", ctypes.c_int32),
+                ("two_groups", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("n_timed", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("default_s", ctypes.c_double), ("best_s", ctypes.c_double), ("tuning_s", ctypes.c_double)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
@@ -100,6 +107,8 @@ def lib():
                                      _c_double_p, ctypes.POINTER(Options)]
     L.pcv_eval.argtypes = [P, ctypes.POINTER(Theta), _c_double_p, ctypes.POINTER(EvalReport)]
     L.pcv_eval_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p]
+    L.pcv_autotune.argtypes = [P, ctypes.POINTER(Theta), ctypes.c_char_p, ctypes.c_int32,
+                               ctypes.POINTER(TuneReport)]
     L.pcv_eval_batch_ex.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Theta), _c_double_p,
                                     ctypes.POINTER(EvalReport)]
     L.pcv_factor.argtypes = [P, ctypes.POINTER(Theta)]
@@ -328,6 +337,14 @@ class Problem:
         d.update(per_subset_sspe=z, per_subset_logdet=ld, per_subset_iters=it,
                  per_subset_neg2loglik=nll)
         return loss.value, d
+
+    def autotune(self, th, cache=None, reps=3):
+        """Pick the launch shapes and schedule by timing pcv_eval at th
+        (pcv_autotune); returns the chosen configuration and timings."""
+        r = TuneReport()
+        _check(lib().pcv_autotune(self._handle(), ctypes.byref(th),
+                                  None if cache is None else os.fsencode(cache), int(reps), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in TuneReport._fields_ if k != "pad0"}
 
     def eval_batch(self, thetas, report=False):
         """Losses of several theta values, evaluated together; with
