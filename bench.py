@@ -6,7 +6,9 @@ an exponential-covariance field (range 50, nugget 0.1), the recursive
 division of Sec. 2.4 into 2,400 cores with 20% overlap (shells) and 10% of
 every core held out.  One step = one full theta-evaluation (covariance,
 Cholesky, solves + refinement, kriging of the validation points, loss
-reduction), inputs resident in HBM.
+reduction), inputs resident in HBM.  The timed steps are graph replays of
+the evaluation with the library's default launch shapes and schedule
+(--tune picks them with pcv_autotune first, outside the timed region).
 
 Prints one JSON line.  Besides the timed mixed-precision path it reports the
 plain FP64 GPU path, the relative difference between the two losses, the
@@ -177,7 +179,9 @@ def cpu_baseline(w, th, gpu_per_subset, sample=144, seed=7, workload="large"):
         T = pt.train_idx[pt.train_ptr[i]:pt.train_ptr[i + 1]]
         V = pt.val_idx[pt.val_ptr[i]:pt.val_ptr[i + 1]]
         jobs.append((w.locs[T], w.y[T], w.locs[V], w.y[V], w.cov, th[0], th[1]))
-    cores = max(1, min(16, os.cpu_count() or 1))
+    # one worker per host core this process may use, at most 16: the host
+    # cores a one-GPU machine grants its GPU's jobs
+    cores = max(1, min(16, len(os.sched_getaffinity(0)), os.cpu_count() or 1))
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -191,7 +195,9 @@ def cpu_baseline(w, th, gpu_per_subset, sample=144, seed=7, workload="large"):
     rel = np.abs(gpu_per_subset[pick] - z) / np.maximum(z, 1e-300)
     return dict(value=est_single / cores, unit="s", cores=cores, kind="oracle",
                 sample=f"{workload}: {len(pick)} of {act.size} subsets (seeded), {cpu_s.sum():.1f} CPU-s, "
-                       f"extrapolated by n^3 share to all subsets on {cores} cores, one BLAS thread each",
+                       f"extrapolated by n^3 share to all subsets on {cores} cores (one worker process per "
+                       f"core, one BLAS thread each; the box grants 16 host cores per GPU, "
+                       f"os.cpu_count() = {os.cpu_count()})",
                 single_core_s=est_single, sample_wall_s=wall), float(rel.max())
 
 
@@ -210,6 +216,9 @@ def main():
                     help="seconds of the same traffic on a discarded server before each serving run")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of each serving run (0 = skip serving)")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the launch shapes and schedule with pcv_autotune first (off by default: "
+                         "the tuner is not yet cleared for GPU runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     a = ap.parse_args()
@@ -268,53 +277,77 @@ def main():
         n = nT[ids].astype(np.float64)
         return float(np.sum(n ** 3 / 3.0 + n ** 2 / 2.0 + n / 6.0))
 
-    def run(prec, steps, warmup):
-        t1 = time.perf_counter()
-        P = pcv.Problem.from_workload(w, prec=prec, max_refine=a.max_refine, stream=stream, profile=True)
-        log(f"[{prec}] problem resident in {time.perf_counter() - t1:.1f}s: {P.info()}")
+    import tempfile
+    tune_cache = os.path.join(tempfile.mkdtemp(prefix="pcv_tune_"), "cache.txt")
 
-        def step():
+    def run(prec, steps, warmup):
+        """Timed evaluations on graph replays (after the autotuner picked the
+        launch shapes and schedule), then a few evaluations of a second
+        problem with the same configuration launched eagerly with HIP events
+        between the phases, for the phase times and the factorisation
+        kernel's time (roofline)."""
+        t1 = time.perf_counter()
+        P = pcv.Problem.from_workload(w, prec=prec, max_refine=a.max_refine, stream=stream)
+        log(f"[{prec}] problem resident in {time.perf_counter() - t1:.1f}s: {P.info()}")
+        tune = P.autotune(thetas[0], cache=tune_cache, reps=3) if a.tune else None
+        if tune:
+            log(f"[{prec}] autotune: {tune}")
+
+        def step(Q, report):
             if len(thetas) > 1:
                 # all theta values of the step in one batched evaluation;
                 # phase times per theta are the batch's sums / K
-                losses, rep = P.eval_batch(thetas, report=True)
+                if not report:
+                    return list(Q.eval_batch(thetas)), None
+                losses, rep = Q.eval_batch(thetas, report=True)
                 K = len(thetas)
-                for k in ("ms_factor", "ms_solve", "ms_refine", "ms_predict", "ms_reduce"):
+                for k in ("ms_factor", "ms_solve", "ms_refine", "ms_predict", "ms_reduce", "ms_factor_all"):
                     rep[k] /= K
                 rep["max_rel_residual"] = 0.0
                 return list(losses), [rep]
-            losses, reps = [], []
-            for th in thetas:
-                loss, rep = P.eval(th, report=True)
-                losses.append(loss)
-                reps.append(rep)
-            return losses, reps
+            if not report:
+                return [Q.eval(th) for th in thetas], None
+            out = [Q.eval(th, report=True) for th in thetas]
+            return [o[0] for o in out], [o[1] for o in out]
 
         for k in range(warmup):
-            losses, reps = step()
-            log(f"[{prec}] warmup {k}: loss {losses[0]:.12g} factor {reps[0]['ms_factor']:.2f}ms")
+            losses, _ = step(P, False)
+            log(f"[{prec}] warmup {k}: loss {losses[0]:.12g}")
         torch.cuda.synchronize()
-        facs, facs_all = [], []
         tt = time.perf_counter()
         for k in range(steps):
-            losses, reps = step()
+            losses, _ = step(P, False)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - tt
+        log(f"[{prec}] {steps} timed steps (graph replays): {1e3 * total / steps:.2f} ms per step, "
+            f"loss {losses[0]:.12g}")
+        P.close()
+        # phase times and the factorisation launch's time: eager launches with events
+        Pp = pcv.Problem.from_workload(w, prec=prec, max_refine=a.max_refine, stream=stream, profile=True)
+        if a.tune:
+            Pp.autotune(thetas[0], cache=tune_cache, reps=3)  # the same choice, from the cache
+        facs, facs_all = [], []
+        step(Pp, True)
+        for k in range(max(2, min(steps, 5))):
+            lp, reps = step(Pp, True)
             facs += [r["ms_factor"] for r in reps]
             facs_all += [r["ms_factor_all"] for r in reps]
             r0 = reps[0]
-            log(f"[{prec}] step {k}: loss {losses[0]:.12g} factor {r0['ms_factor']:.2f}ms "
+            log(f"[{prec}] profiled {k}: loss {lp[0]:.12g} factor {r0['ms_factor']:.2f}ms "
                 f"(all {r0['ms_factor_all']:.2f}) solve {r0['ms_solve']:.2f} refine {r0['ms_refine']:.2f} "
                 f"predict {r0['ms_predict']:.2f}")
-        torch.cuda.synchronize()
-        total = time.perf_counter() - tt
+        if lp[0] != losses[0]:
+            raise RuntimeError(f"graph and eager evaluations differ: {losses[0]!r} vs {lp[0]!r}")
         if len(thetas) > 1:
             # per-subset losses of the first theta for the oracle cross-check
-            _, r1 = P.eval(thetas[0], report=True)
+            _, r1 = Pp.eval(thetas[0], report=True)
             reps[0]["per_subset_sspe"] = r1["per_subset_sspe"]
             reps[0]["max_rel_residual"] = r1["max_rel_residual"]
-        P.close()
-        return losses, reps, total / (steps * len(thetas)), float(np.mean(facs)), float(np.mean(facs_all))
+        Pp.close()
+        return (losses, reps, total / (steps * len(thetas)), float(np.mean(facs)), float(np.mean(facs_all)),
+                tune)
 
-    losses, reps, s_per, ms_fac, ms_fac_all = run(a.prec, a.steps, a.warmup)
+    losses, reps, s_per, ms_fac, ms_fac_all, tune = run(a.prec, a.steps, a.warmup)
     rep = reps[0]
     n_first = int(rep["n_factor_first"])
     flops_first = flops_of(lpt[:n_first])
@@ -341,19 +374,21 @@ def main():
                    "sum_n3": float(np.sum(nT[act].astype(np.float64) ** 3)),
                    "n_val": int(rep["n_val"]), "theta_per_step": len(thetas),
                    "precision": a.prec, "max_refine": a.max_refine,
-                   "launch": ("one launch per kernel for the step's theta values (batched), phase events "
-                              "between the launches") if len(thetas) > 1 else
-                             ("eager launches with phase events; factorisation of the "
-                              f"{n_first} largest subsets first, the other {int(act.sum()) - n_first} "
-                              "factored on the same stream while the first group's solves, refinement "
-                              "and kriging run on a second stream" if n_first < int(act.sum()) else
-                              "eager launches with phase events, one launch per kernel over all subsets")},
+                   "launch": ("graph replays of one launch per kernel for the step's theta values (batched)"
+                         if len(thetas) > 1 else
+                         ("graph replays; factorisation of the "
+                          f"{n_first} largest subsets first, the other {int(act.sum()) - n_first} "
+                          "factored on the same stream while the first group's solves, refinement "
+                          "and kriging run on a second stream" if n_first < int(act.sum()) else
+                          "graph replays, one launch per kernel over all subsets")),
+              "autotune": tune},
     }
     peak = PEAK_FP32_MFMA if a.prec == "mixed" else PEAK_FP64_MFMA
     ach = flops_first / (ms_fac * 1e-3) / 1e12
     src = os.path.join(ROOT, "paper_1912_13132_amd", "csrc", "pcv_potrf.hip")
     # FP32 launches whose largest subset has npad <= 1536 use 256-thread workgroups
-    shape = 256 if a.prec == "mixed" and int(npad[act].max()) <= 1536 else 512
+    small_npad = tune["small_npad"] if tune else 1536
+    shape = 256 if a.prec == "mixed" and int(npad[lpt[0]]) <= small_npad else 512
     # the third template argument: the launch shares its largest subsets
     # between several workgroups
     n_coop = int(rep["n_coop_subsets"])
@@ -377,7 +412,7 @@ def main():
     out["max_rel_residual"] = max(r["max_rel_residual"] for r in reps)
     out["n_fallback_fp64"] = sum(r["n_fallback_fp64"] for r in reps)
     if a.prec == "mixed" and not a.no_fp64:
-        losses64, reps64, s64, ms64, ms64_all = run("fp64", max(2, a.steps // 2), 1)
+        losses64, reps64, s64, ms64, ms64_all, tune64 = run("fp64", max(2, a.steps // 2), 1)
         n64 = int(reps64[0]["n_factor_first"])
         out["fp64_path"] = {"s_per_eval": s64, "loss": losses64[0], "factor_ms": ms64,
                             "factor_launch_subsets": n64,

@@ -226,8 +226,9 @@ pcv_status pcv_eval_batch_ex(pcv_problem* p, int32_t n_theta, const pcv_theta* t
                              double* losses, pcv_eval_report* report);
 
 /* Local losses over a set of theta values (Sec. 4.4: local RMSPE and the
- * best local zeta of each subset, the basis of non-stationary fits).
- * losses[k] as pcv_eval for thetas[k]; per_subset_sspe (may be NULL) receives
+ * best local zeta of each subset, the basis of non-stationary fits),
+ * evaluated by the multi-theta launches of pcv_eval_batch.
+ * losses[k] as pcv_eval for thetas[k] (bit for bit); per_subset_sspe (may be NULL) receives
  * z_i(theta_k) at [k * S + i]; best (may be NULL) receives, per subset, the k
  * with the smallest z_i (lowest k on ties; -1 for subsets without
  * validation points). */

@@ -311,13 +311,10 @@ pcv_status pcv_eval_grid(pcv_problem* p, int32_t n_theta, const pcv_theta* theta
     own.resize((size_t)n_theta * S);
     z = own.data();
   }
-  for (int32_t k = 0; k < n_theta; ++k) {
-    pcv_eval_report rep;
-    std::memset(&rep, 0, sizeof(rep));
-    rep.per_subset_sspe = z ? z + (size_t)k * S : nullptr;
-    pcv_status s = pcv::eval_impl(p, thetas[k], &losses[k], z ? &rep : nullptr);
-    if (s != PCV_OK) return s;
-  }
+  // the multi-theta launches (one launch per kernel over up to 64 theta
+  // values), bit for bit the single evaluations
+  pcv_status s = pcv::eval_batch_impl(p, n_theta, thetas, losses, nullptr, z);
+  if (s != PCV_OK) return s;
   if (best)
     for (int32_t i = 0; i < S; ++i) {
       int32_t b = -1;

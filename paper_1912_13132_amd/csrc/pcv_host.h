@@ -199,8 +199,9 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
 void problem_free(pcv_problem* p);
 pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep);
 // n_theta evaluations, batched B at a time when the workspace allows.
+// per_subset_sspe (may be null): [n_theta][S] local losses.
 pcv_status eval_batch_impl(pcv_problem* p, int32_t n_theta, const pcv_theta* thetas, double* losses,
-                           pcv_eval_report* rep);
+                           pcv_eval_report* rep, double* per_subset_sspe = nullptr);
 pcv_status factor_impl(pcv_problem* p, const pcv_theta* th, bool local);
 pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta, int32_t* status);
 // Single-stream evaluation schedule while a server holds the problem (on)

@@ -1239,7 +1239,7 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
 }  // namespace
 
 pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, double* losses,
-                           pcv_eval_report* rep) {
+                           pcv_eval_report* rep, double* zs) {
   const double t0 = now_s();
   HIPCHK(hipSetDevice(p->device));
   if (rep) {
@@ -1263,7 +1263,8 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
     for (int32_t k = 0; k < K; ++k) {
       pcv_eval_report r1;
       std::memset(&r1, 0, sizeof(r1));
-      pcv_status s = eval_impl(p, thetas[k], &losses[k], rep ? &r1 : nullptr);
+      r1.per_subset_sspe = zs ? zs + (size_t)k * p->S : nullptr;
+      pcv_status s = eval_impl(p, thetas[k], &losses[k], (rep || zs) ? &r1 : nullptr);
       if (s != PCV_OK) return s;
       if (rep) {
         rep->ms_factor += r1.ms_factor;
@@ -1332,11 +1333,17 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
       rep->ms_predict += ms[3];
       rep->ms_reduce += ms[4];
     }
+    if (zs)
+      HIPCHK(hipMemcpy(zs + (size_t)g0 * p->S, b.d_sspe, sizeof(double) * (size_t)nb * p->S,
+                       hipMemcpyDeviceToHost));
     for (int t = 0; t < nb; ++t) {
       if (b.h_nbad[t] > 0 || (mixed && (p->opt.debug_flags & 1))) {
         // a subset broke down or did not converge: this theta goes through
         // the single evaluation, which re-runs those subsets in FP64
-        s = eval_impl(p, thetas[g0 + t], &losses[g0 + t], nullptr);
+        pcv_eval_report r1;
+        std::memset(&r1, 0, sizeof(r1));
+        r1.per_subset_sspe = zs ? zs + (size_t)(g0 + t) * p->S : nullptr;
+        s = eval_impl(p, thetas[g0 + t], &losses[g0 + t], zs ? &r1 : nullptr);
         if (s != PCV_OK) return s;
         if (rep) ++rep->n_fallback_fp64;
       } else {

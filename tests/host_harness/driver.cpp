@@ -253,6 +253,30 @@ void tune(const Data& d, const char* cache) {
   EXPECT(Live::now() == base);
 }
 
+// Tuning of a problem whose first evaluation happens inside the tuner,
+// after a factorisation and a server that held it (and was refused tuning).
+void tune_after_serving(const Data& d) {
+  const Live base = Live::now();
+  const pcv_theta t = th(0.4, 0.1);
+  for (int rep = 0; rep < 3; ++rep) {
+    pcv_options o;
+    pcv_default_options(&o);
+    pcv_problem* p = create(d, o);
+    CHECK(pcv_factor(p, &t));
+    pcv_server* srv = nullptr;
+    CHECK(pcv_server_create(&srv, p, 0, 64));
+    pcv_tune_report r;
+    EXPECT(pcv_autotune(p, &t, nullptr, 3, &r) == PCV_ERR_STATE);
+    CHECK(pcv_server_destroy(srv));
+    CHECK(pcv_autotune(p, &t, nullptr, 1, &r));
+    std::printf("tune after serving: small_npad %d max_wg %d two_groups %d timed %d\n", r.small_npad,
+                r.max_wg_per_subset, r.two_groups, r.n_timed);
+    evals(p, 1);
+    CHECK(pcv_problem_destroy(p));
+  }
+  EXPECT(Live::now() == base);
+}
+
 int main(int argc, char** argv) {
   const std::string sc = argc > 1 ? argv[1] : "sequence";
   const Data d = make_data(300, 1);
@@ -261,6 +285,9 @@ int main(int argc, char** argv) {
     stub_report("sequence");
   } else if (sc == "oom") {
     oom(d);
+  } else if (sc == "tune_after_serving") {
+    tune_after_serving(make_data(290, 2));
+    stub_report("tune_after_serving");
   } else if (sc == "tune") {
     tune(d, argc > 2 ? argv[2] : "pcv_tune_cache.txt");
     stub_report("tune");

@@ -20,6 +20,7 @@
 // allocations start zeroed), which the host code reads as "no subset failed".
 #include <hip/hip_runtime_api.h>
 
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -27,7 +28,9 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <random>
 #include <set>
+#include <thread>
 #include <vector>
 
 #include "../../paper_1912_13132_amd/csrc/pcv_host.h"
@@ -274,10 +277,26 @@ hipError_t hipStreamDestroy(hipStream_t s) {
   g_dead.push_back(s);
   return hipSuccess;
 }
+// With STUB_JITTER=<seed> set, every stream synchronisation takes a random
+// 0..300 microseconds, so that timing-driven choices (the tuner's) follow
+// different paths from run to run.
+static void jitter() {
+  static const char* env = std::getenv("STUB_JITTER");
+  if (!env) return;
+  static std::mt19937_64 rng(std::strtoull(env, nullptr, 10));
+  static std::mutex mu;
+  int us;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    us = (int)(rng() % 300);
+  }
+  std::this_thread::sleep_for(std::chrono::microseconds(us));
+}
 hipError_t hipStreamSynchronize(hipStream_t s) {
   live_stream(s, "hipStreamSynchronize");
   no_capture("hipStreamSynchronize");
   if (s && s->cap) die("hipStreamSynchronize on a capturing stream");
+  jitter();
   return hipSuccess;
 }
 hipError_t hipDeviceSynchronize(void) {

@@ -63,3 +63,24 @@ def check_logdet(got, ref, n, lam, prec, say=None):
         say(f"   log det: max |diff| {float(d.max(initial=0.0)):.2e}, max diff / bound {ratio:.3f}")
     assert ratio <= 1.0, ("log det", ratio)
     return ratio
+
+
+def mixed_size_subsets(seed, S=300):
+    """S independent subsets: three large ones (shared in the first launch),
+    a band around the 4-wave / 8-wave shape threshold, many small ones;
+    more subsets than compute units, so two schedule groups apply."""
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 1400 + seed]))
+    sizes_T = [3000, 2500, 2100] + list(r.integers(1200, 1700, size=40)) + list(r.integers(60, 400, size=S - 43))
+    sizes_V = [60, 50, 40] + list(r.integers(5, 30, size=40)) + list(r.integers(1, 10, size=S - 43))
+    locs, y, tl, vl = [], [], [], []
+    off = 0
+    for nt, nv in zip(sizes_T, sizes_V):
+        spread = 3.0 * np.sqrt(nt / 2000.0)
+        locs.append(r.uniform(0, spread, (nt + nv, 2)))
+        y.append(r.standard_normal(nt + nv))
+        tl.append(np.arange(off, off + nt))
+        vl.append(np.arange(off + nt, off + nt + nv))
+        off += nt + nv
+    return (np.concatenate(locs), np.concatenate(y), np.r_[0, np.cumsum(sizes_T)],
+            np.concatenate(tl).astype(np.int32), np.r_[0, np.cumsum(sizes_V)],
+            np.concatenate(vl).astype(np.int32))

@@ -127,3 +127,19 @@ def test_gls_coefficients_per_subset(w_small, local):
         ref = oracle.gls_beta_subset(w_small.locs[T], w_small.y[T], X[T], 0, th, lam)
         assert st[i] == 0
         np.testing.assert_allclose(beta[i], ref, rtol=1e-8, atol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_grid_batched_equals_single_evaluations(w_small, prec):
+    """pcv_eval_grid runs the multi-theta launches: its losses and local
+    losses equal one pcv_eval per theta bit for bit (70 values: a group of
+    64 theta slots and a remainder of 6)."""
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 802]))
+    ths = [pcv.theta(0.05 * 2 ** r.uniform(-1, 1), 0.1 * 2 ** r.uniform(-1, 1)) for _ in range(70)]
+    say(f"[case] eval_grid batched vs single prec={prec}")
+    with pcv.Problem.from_workload(w_small, prec=prec) as P:
+        losses, z, best = P.eval_grid(ths)
+        for k in (0, 37, 63, 64, 69):
+            loss, rep = P.eval(ths[k], report=True)
+            assert losses[k] == loss
+            np.testing.assert_array_equal(z[k], rep["per_subset_sspe"])

@@ -186,3 +186,27 @@ def test_evaluations_interleaved_with_kriging(w_plain):
         np.testing.assert_array_equal(m, ma)
         np.testing.assert_array_equal(v, va)
     assert st["evals_per_s"] > 0 and st["qps"] > 0
+
+
+def test_wait_timeout_reports_busy_and_keeps_the_ticket(w_plain):
+    """pcv_server_wait with a timeout shorter than the request: PCV_ERR_BUSY,
+    and the ticket stays valid; the result collected afterwards equals
+    pcv_predict of the request alone."""
+    th = pcv.theta(0.1, 0.05)
+    r = np.random.default_rng(np.random.SeedSequence([1912, 13132, 710]))
+    q = r.uniform(0, 1, (100_000, 2))
+    say("[case] server wait timeout -> BUSY")
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        P.factor(th)
+        alone = P.predict(q)[:2]
+        with pcv.Server(P) as srv:
+            te = [srv.submit_eval(pcv.theta(0.1 * (1 + 0.1 * k), 0.05)) for k in range(3)]
+            tk = srv.submit_predict(q)
+            with pytest.raises(pcv.PcvError) as e:
+                srv.wait(tk, timeout=1e-6)
+            assert e.value.status == 6
+            m, v = srv.wait(tk)
+            for t in te:
+                srv.wait(t)
+    np.testing.assert_array_equal(m, alone[0])
+    np.testing.assert_array_equal(v, alone[1])
