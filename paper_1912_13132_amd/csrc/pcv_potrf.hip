@@ -173,15 +173,18 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB]
 // (NW >= 4).
 //
 // Blocked in 16 x 16 tiles.  For each tile column kb:
-//   1. wave 0 factors the diagonal tile in registers, four entries per lane:
-//      at pivot j the pivot is broadcast with readlane and the column-j
-//      entries each lane needs come by lane shuffles; then lane c builds
-//      column c of the tile's inverse by forward substitution from LDS;
-//   2. the tiles below: X_I = A_Ik L_kk^{-T}, one FP64 MFMA tile per wave;
+//   1. wave 0 factors and inverts the diagonal tile together in registers,
+//      four entries per lane: at pivot j the pivot comes by readlane, the
+//      lane's own row entry by a quad broadcast (DPP), the column-j entries
+//      and the inverse's row j by lane shuffles; the inverse is built as the
+//      product of the elementary inverses of the columns (row j scaled by
+//      1/L_jj, the rows below eliminated with it);
+//   2. the tiles below: X_I = A_Ik L_kk^{-T}, one FP64 MFMA tile per wave,
+//      and beside them row kb of the inverse off the diagonal, one tile per
+//      wave: Inv_kb,J = -Inv_kb,kb * sum_{J<=K<kb} L_kb,K Inv_K,J (two MFMA
+//      products), from the leaf of this step and the rows of earlier steps;
 //   3. the trailing lower block triangle: A_IK -= X_I X_K^T, one MFMA tile
 //      per wave.
-// Inverse off the diagonal, by distance d = I - J, one tile per wave:
-//   Inv_IJ = -Inv_II * sum_{J<=K<I} L_IK Inv_KJ   (two MFMA products).
 __device__ __forceinline__ double rlane(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
@@ -189,8 +192,27 @@ __device__ __forceinline__ double rlane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// quad_perm DPP control that broadcasts lane q of every group of four
+constexpr int QP(int q) { return q | q << 2 | q << 4 | q << 6; }
+template <int CTRL>
+__device__ __forceinline__ double qbcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// value of lane (l & ~3) | q in every lane l (q known after unrolling)
+__device__ __forceinline__ double qbcast(double v, int q) {
+  switch (q) {
+    case 0: return qbcast<QP(0)>(v);
+    case 1: return qbcast<QP(1)>(v);
+    case 2: return qbcast<QP(2)>(v);
+    default: return qbcast<QP(3)>(v);
+  }
+}
+
 template <int NW>
-__device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], double* rdiag, int nreal, int grow0,
+__device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], int nreal, int grow0,
                                    double& ld, int& bad) {
   typedef double f64x4_t __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -204,75 +226,62 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
     //    by lane shuffles; then the factored tile goes back to LDS.
     if (w == 0) {
       const int r = l >> 2, cq = l & 3;
-      double a[4];
+      double a[4], x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = Dg[k0 + r][k0 + cq + 4 * u];
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Dg[k0 + r][k0 + cq + 4 * u];
+        x[u] = r == cq + 4 * u ? 1.0 : 0.0;
+      }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int uj = j >> 2, qj = j & 3;
+        // operands of this pivot that need no pivot value: issued first
+        double xj[4], acj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xj[u] = __shfl(x[u], 4 * j + cq, 64);
+          acj[u] = __shfl(a[uj], 4 * (cq + 4 * u) + qj, 64);
+        }
+        const double arj = qbcast(a[uj], qj);
         double p = rlane(a[uj], 4 * j + qj);
         const bool ok = p > 0.0 && p < 1e300;
         if (!ok) p = 1.0;
         if (l == 0 && !ok && !bad) bad = grow0 + k0 + j + 1;
-        // 1/sqrt(p): hardware estimate refined by two Newton steps (error far below
-        // FP64 rounding), then sqrt(p) = p / sqrt(p)
         double isp = __builtin_amdgcn_rsq(p);
         isp = isp * (1.5 - 0.5 * p * isp * isp);
         isp = isp * (1.5 - 0.5 * p * isp * isp);
         const double sp = p * isp, ip = isp * isp;
-        if (l == 0) rdiag[k0 + j] = isp;
-        const double arj = __shfl(a[uj], (l & ~3) | qj, 64);
         const double arjp = arj * ip;
-        double upd[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) upd[u] = a[u] - arjp * __shfl(a[uj], 4 * (cq + 4 * u) + qj, 64);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = cq + 4 * u;
+          const double upd = fma(-arjp, acj[u], a[u]);
           if (c == j && r >= j) a[u] = r == j ? sp : arj * isp;
-          if (c > j && r >= c) a[u] = upd[u];
+          if (c > j && r >= c) a[u] = upd;
+          // inverse: row j scaled, the rows below eliminated with it
+          x[u] = r == j ? x[u] * isp : (r > j ? fma(-arjp, xj[u], x[u]) : x[u]);
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (r >= cq + 4 * u) Dg[k0 + r][k0 + cq + 4 * u] = a[u];
-    }
-    __syncthreads();
-    if (w == 0) {
+      for (int u = 0; u < 4; ++u) {
+        const int c = cq + 4 * u;
+        if (r >= c) {
+          Dg[k0 + r][k0 + c] = a[u];
+          Dg[k0 + c][k0 + r + 1] = x[u];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
       // log det of the tile's real rows
       double t = (l < 16 && k0 + l < nreal) ? 2.0 * log(Dg[k0 + l][k0 + l]) : 0.0;
 #pragma unroll
       for (int off = 8; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
       if (tid == 0) ld += t;
-      int c = li;
-      asm volatile("" : "+v"(c));
-      // inverse of the tile, lane c building column c by forward substitution
-      // over the stored factor (wave-ordered LDS: no barrier needed)
-      __builtin_amdgcn_wave_barrier();
-      double y[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) y[r] = r == c ? 1.0 : 0.0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const double yj = y[j] * rdiag[k0 + j];
-        y[j] = yj;
-#pragma unroll
-        for (int r = j + 1; r < 16; ++r) y[r] = fma(-Dg[k0 + r][k0 + j], yj, y[r]);
-        asm volatile("" : "+v"(y[0]), "+v"(y[1]), "+v"(y[2]), "+v"(y[3]), "+v"(y[4]), "+v"(y[5]), "+v"(y[6]),
-                     "+v"(y[7]), "+v"(y[8]), "+v"(y[9]), "+v"(y[10]), "+v"(y[11]), "+v"(y[12]), "+v"(y[13]),
-                     "+v"(y[14]), "+v"(y[15])
-                     :
-                     : "memory");
-      }
-      if (l < 16) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          if (r >= c) Dg[k0 + c][k0 + r + 1] = y[r];
-      }
     }
     __syncthreads();
-    if (kb == 3) break;
-    // ---- tiles below: X_I = A_I,k L_kk^{-T} (MFMA), wave w -> block row kb + 1 + w
+    // ---- tiles below, X_I = A_I,k L_kk^{-T}, wave w -> block row kb + 1 + w; and
+    //      row kb of the inverse, Inv_kb,J = -Inv_kb,kb sum_{K=J}^{kb-1} L_kb,K Inv_K,J
+    //      for J < kb, wave 3 - kb + J: both need only this step's leaf and the
+    //      earlier steps
     if (w < 3 - kb) {
       const int I = kb + 1 + w;
       f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
@@ -285,8 +294,34 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) Dg[16 * I + 4 * v + kq][k0 + li] = acc[v];
+    } else if (w < 3) {
+      const int I = kb, J = w - (3 - kb);
+      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < I; ++K) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int m = 4 * ks + kq;
+          const double av = Dg[16 * I + li][16 * K + m];
+          const double bv = (K > J || m >= li) ? Dg[16 * J + li][16 * K + m + 1] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tb[J][4 * v + kq][li] = acc[v];
+      __builtin_amdgcn_wave_barrier();
+      f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int m = 4 * ks + kq;
+        const double av = m <= li ? -Dg[16 * I + m][16 * I + li + 1] : 0.0;
+        const double bv = Tb[J][m][li];
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc2, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dg[16 * J + li][16 * I + 4 * v + kq + 1] = acc2[v];
     }
     __syncthreads();
+    if (kb == 3) break;
     // ---- trailing update of the lower block triangle: A_IK -= X_I X_K^T
     {
       const int t = 3 - kb;
@@ -313,37 +348,6 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], doub
         for (int v = 0; v < 4; ++v)
           if (I != K || li <= 4 * v + kq) Dg[16 * I + 4 * v + kq][16 * K + li] = acc[v];
       }
-    }
-    __syncthreads();
-  }
-  // ---- off-diagonal tiles of the inverse by distance d = I - J:
-  //      Inv_IJ = -Inv_II * sum_{K=J}^{I-1} L_IK Inv_KJ
-  for (int d = 1; d < 4; ++d) {
-    if (w < 4 - d) {
-      const int I = d + w, J = w;
-      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-      for (int K = J; K < I; ++K) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int m = 4 * ks + kq;
-          const double av = Dg[16 * I + li][16 * K + m];
-          const double bv = (K > J || m >= li) ? Dg[16 * J + li][16 * K + m + 1] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Tb[w][4 * v + kq][li] = acc[v];
-      __builtin_amdgcn_wave_barrier();
-      f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int m = 4 * ks + kq;
-        const double av = m <= li ? -Dg[16 * I + m][16 * I + li + 1] : 0.0;
-        const double bv = Tb[w][m][li];
-        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc2, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Dg[16 * J + li][16 * I + 4 * v + kq + 1] = acc2[v];
     }
     __syncthreads();
   }
@@ -420,7 +424,6 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   __shared__ __attribute__((aligned(16))) char smem_u[SM::U];
   __shared__ __attribute__((aligned(16))) T InvS[SM::NSUB][64 * LDI];
   __shared__ double Tb[3][16][17];
-  __shared__ double rdiag[64];
   __shared__ T colx[PB], coly[PB];  // the current panel's column coordinates
 
   T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
         __syncthreads();
         if (tid < 64) Dg[tid][tid] = c0 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
         __syncthreads();
-        diag_factor_invert<SM::NW>(Dg, Tb, rdiag, n - c0, c0, ld, bad);
+        diag_factor_invert<SM::NW>(Dg, Tb, n - c0, c0, ld, bad);
         for (int e = tid; e < 64 * 64; e += NT) {
           const int i = e >> 6, j = e & 63;
           L[packed_rowoff32(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
@@ -703,7 +706,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
             __syncthreads();
             if (tid < 64) Dg[tid][tid] = c0 + 64 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
             __syncthreads();
-            diag_factor_invert<SM::NW>(Dg, Tb, rdiag, n - c0 - 64, c0 + 64, ld, bad);
+            diag_factor_invert<SM::NW>(Dg, Tb, n - c0 - 64, c0 + 64, ld, bad);
             for (int e = tid; e < 64 * 64; e += NT) {
               const int i = e >> 6, j = e & 63;
               L[packed_rowoff32(c0 + 64 + i) + c0 + 64 + j] = j <= i ? (T)Dg[i][j] : (T)0;
