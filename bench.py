@@ -387,8 +387,11 @@ def main():
     ach = flops_first / (ms_fac * 1e-3) / 1e12
     src = os.path.join(ROOT, "paper_1912_13132_amd", "csrc", "pcv_potrf.hip")
     # FP32 launches whose largest subset has npad <= 1536 use 256-thread workgroups
+    # FP32 launches take 2-wave work-groups up to npad 704, 4-wave ones up to
+    # the small-shape threshold, 8-wave ones above (from the launch's largest subset)
     small_npad = tune["small_npad"] if tune else 1536
-    shape = 256 if a.prec == "mixed" and int(npad[lpt[0]]) <= small_npad else 512
+    first_npad = int(npad[lpt[0]])
+    shape = (128 if first_npad <= 704 else 256 if first_npad <= small_npad else 512) if a.prec == "mixed" else 512
     # the third template argument: the launch shares its largest subsets
     # between several workgroups
     n_coop = int(rep["n_coop_subsets"])

@@ -95,10 +95,15 @@ struct CoopPlan {
 // counts launch blocks (with cp, the cooperative blocks included; cp needs
 // the 8-wave shape).
 constexpr int FACTOR_SMALL_NPAD = 1536;
+// ... and those whose largest subset has npad <= tiny_npad 2-wave
+// workgroups (64-column panels, 64-row chunks, four per compute unit);
+// measured on uniform sizes: faster up to n = 600, equal at 700, slower
+// from 800.
+constexpr int FACTOR_TINY_NPAD = 704;
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
                             int32_t* status, const CoopPlan* cp = nullptr,
-                            int small_npad = FACTOR_SMALL_NPAD);
+                            int small_npad = FACTOR_SMALL_NPAD, int tiny_npad = FACTOR_TINY_NPAD);
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
                             const double* cy, double* Lbuf, double* Inv, double* logdet,
                             int32_t* status, const CoopPlan* cp = nullptr);

@@ -1,7 +1,8 @@
 // Batched blocked Cholesky of the subset matrices M_i = Sigma_i(theta) +
 // lambda I (the (Sigma + lambda I)^{-1} of eq. (3), arXiv:1912.13132), one
 // workgroup per subset: 8 waves (one workgroup per compute unit) or, for
-// small FP32 subsets, 4 waves with 64-column panels (two per compute unit).
+// small FP32 subsets, 4 waves with 64-column panels (two per compute unit),
+// or for the smallest 2 waves with 64-row chunks (four per compute unit).
 //
 // Left-looking over column panels of PB columns (PB = 128 for FP32, 64 for
 // FP64 and for the small shape).  For every panel J and every chunk of 32
@@ -118,11 +119,18 @@ constexpr int LDD = 65;   // FP64 diagonal array row stride (doubles)
 // Cfg<T>::PB columns and 256-row chunks, one workgroup per compute unit (the
 // large subsets).  256: 64-column panels and 128-row chunks in at most 80 KB
 // of LDS, so that two workgroups share a compute unit and one's diagonal
-// block latency overlaps the other's MFMA work (small subsets).
+// block latency overlaps the other's MFMA work.  128 (TINY): 64-column
+// panels and 64-row chunks (the first chunk of a panel is its diagonal
+// block) in 40 KB of LDS: each wave keeps the inverse tiles its triangular
+// solves read in registers instead of LDS, and the FP64 work tiles of the
+// diagonal block share the stage buffers' space, so that four workgroups
+// share a compute unit and their diagonal blocks overlap each other's MFMA
+// work (the smallest subsets).
 template <typename T, int NTH>
 struct Shape {
   static constexpr int NT = NTH;
   static constexpr int NW = NTH / 64;
+  static constexpr bool TINY = NTH == 128;
   static constexpr int PB = NTH == 512 ? Cfg<T>::PB : 64;
   static constexpr int KC = Cfg<T>::KC;
   static constexpr int RCH = NW * WR;         // chunk rows
@@ -130,10 +138,13 @@ struct Shape {
   static constexpr int LDK = KC + VW;         // staged row stride (144 bytes)
   static constexpr int LDI = 64 + VW;         // inverse row stride
   static constexpr int NSUB = PB / 64;
+  static constexpr int NINV = TINY ? 0 : NSUB;  // inverse blocks kept in LDS
   static constexpr int STAGE = (PB + RCH) * LDK * (int)sizeof(T);
   static constexpr int L21 = 64 * LDI * (int)sizeof(T);
   static constexpr int DG = 64 * LDD * 8;
-  static constexpr int U0 = 2 * STAGE > DG ? 2 * STAGE : DG;  // two stage buffers
+  static constexpr int TBB = 3 * 16 * 17 * 8;  // FP64 work tiles of the diagonal block
+  static constexpr int DGT = TINY ? DG + TBB : DG;
+  static constexpr int U0 = 2 * STAGE > DGT ? 2 * STAGE : DGT;  // two stage buffers
   static constexpr int U = NSUB == 2 && L21 > U0 ? L21 : U0;
 };
 
@@ -165,12 +176,34 @@ __device__ __forceinline__ void trsm_regs(typename Cfg<T>::acc_t (&acc)[NBI][NB]
   }
 }
 
+// The same solve with the inverse tiles held in registers: inv[bo (bo + 1) / 2
+// + bk][v] = Inv[16 bo + lr][16 bk + crow(g, v)] (zero above the diagonal).
+template <typename T, int B0, int NBI, int NB>
+__device__ __forceinline__ void trsm_regs_r(typename Cfg<T>::acc_t (&acc)[NBI][NB], const T (&inv)[10][4]) {
+  typedef typename Cfg<T>::acc_t acc_t;
+#pragma unroll
+  for (int bo = 3; bo >= 0; --bo) {
+    acc_t tmp[NB];
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj) tmp[bj] = acc_t{};
+#pragma unroll
+    for (int bk = 0; bk <= bo; ++bk)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj)
+          tmp[bj] = Cfg<T>::mma(inv[bo * (bo + 1) / 2 + bk][v], acc[B0 + bk][bj][v], tmp[bj]);
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj) acc[B0 + bo][bj] = tmp[bj];
+  }
+}
+
 // FP64 factorisation of the 64 x 64 block in Dg (lower part), in place,
 // followed by the inverse of the factor, stored transposed in the free upper
 // part: Inv[i][c] (i >= c) lives at Dg[c][i + 1].  Adds 2 sum log L_jj over
 // rows < nreal to ld and records the first failing pivot (1-based global
 // row) in bad (thread 0's copies).  All NW waves of the workgroup take part
-// (NW >= 4).
+// (NW >= 2).
 //
 // Blocked in 16 x 16 tiles.  For each tile column kb:
 //   1. wave 0 factors and inverts the diagonal tile together in registers,
@@ -282,43 +315,45 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], int 
     //      row kb of the inverse, Inv_kb,J = -Inv_kb,kb sum_{K=J}^{kb-1} L_kb,K Inv_K,J
     //      for J < kb, wave 3 - kb + J: both need only this step's leaf and the
     //      earlier steps
-    if (w < 3 - kb) {
-      const int I = kb + 1 + w;
-      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int m = 4 * ks + kq;
-        const double av = Dg[16 * I + li][k0 + m];
-        const double bv = m <= li ? Dg[k0 + m][k0 + li + 1] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Dg[16 * I + 4 * v + kq][k0 + li] = acc[v];
-    } else if (w < 3) {
-      const int I = kb, J = w - (3 - kb);
-      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-      for (int K = J; K < I; ++K) {
+    for (int t = w; t < 3; t += NW) {
+      if (t < 3 - kb) {
+        const int I = kb + 1 + t;
+        f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int m = 4 * ks + kq;
-          const double av = Dg[16 * I + li][16 * K + m];
-          const double bv = (K > J || m >= li) ? Dg[16 * J + li][16 * K + m + 1] : 0.0;
+          const double av = Dg[16 * I + li][k0 + m];
+          const double bv = m <= li ? Dg[k0 + m][k0 + li + 1] : 0.0;
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dg[16 * I + 4 * v + kq][k0 + li] = acc[v];
+      } else {
+        const int I = kb, J = t - (3 - kb);
+        f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+        for (int K = J; K < I; ++K) {
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int m = 4 * ks + kq;
+            const double av = Dg[16 * I + li][16 * K + m];
+            const double bv = (K > J || m >= li) ? Dg[16 * J + li][16 * K + m + 1] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tb[J][4 * v + kq][li] = acc[v];
+        __builtin_amdgcn_wave_barrier();
+        f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int m = 4 * ks + kq;
+          const double av = m <= li ? -Dg[16 * I + m][16 * I + li + 1] : 0.0;
+          const double bv = Tb[J][m][li];
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dg[16 * J + li][16 * I + 4 * v + kq + 1] = acc2[v];
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Tb[J][4 * v + kq][li] = acc[v];
-      __builtin_amdgcn_wave_barrier();
-      f64x4_t acc2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int m = 4 * ks + kq;
-        const double av = m <= li ? -Dg[16 * I + m][16 * I + li + 1] : 0.0;
-        const double bv = Tb[J][m][li];
-        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc2, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Dg[16 * J + li][16 * I + 4 * v + kq + 1] = acc2[v];
     }
     __syncthreads();
     if (kb == 3) break;
@@ -422,13 +457,17 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
 
   __shared__ __attribute__((aligned(16))) char smem_u[SM::U];
-  __shared__ __attribute__((aligned(16))) T InvS[SM::NSUB][64 * LDI];
-  __shared__ double Tb[3][16][17];
+  __shared__ __attribute__((aligned(16))) T InvS[SM::NINV > 0 ? SM::NINV : 1][SM::NINV > 0 ? 64 * LDI : 1];
+  __shared__ double TbS[SM::TINY ? 1 : 3][16][17];
   __shared__ T colx[PB], coly[PB];  // the current panel's column coordinates
 
   T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
   T* L21s = reinterpret_cast<T*>(smem_u);  // [64][LDI]  -L21 (second half update)
   double(*Dg)[LDD] = reinterpret_cast<double(*)[LDD]>(smem_u);
+  // FP64 work tiles of the diagonal block: behind Dg in the TINY shape
+  double(*Tb)[16][17] = SM::TINY ? reinterpret_cast<double(*)[16][17]>(smem_u + SM::DG) : TbS;
+  // TINY: the inverse tiles of the current panel that this wave's solves read
+  T invr[SM::TINY ? 10 : 1][4];
 
   // rank of this workgroup among the nwg that share the subset; blocks past
   // the cooperative ones (and every block without COOP) work alone
@@ -642,11 +681,26 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
           L[packed_rowoff32(c0 + i) + c0 + j] = j <= i ? (T)Dg[i][j] : (T)0;
           const double iv = j <= i ? Dg[j][i + 1] : 0.0;
           Inv[(int64_t)(c0 / 64) * 4096 + e] = iv;
-          InvS[0][i * LDI + j] = (T)iv;
+          if constexpr (SM::NINV > 0) InvS[0][i * LDI + j] = (T)iv;
+        }
+        if constexpr (SM::TINY) {
+#pragma unroll
+          for (int bo = 0; bo < 4; ++bo)
+#pragma unroll
+            for (int bk = 0; bk <= bo; ++bk)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int row = 16 * bo + lr, col = 16 * bk + Cfg<T>::crow(g, v);
+                invr[bo * (bo + 1) / 2 + bk][v] = col <= row ? (T)Dg[col][row + 1] : (T)0;
+              }
         }
         __syncthreads();
       }
-      if (wact && wpos >= 2) trsm_regs<T, 0, NBI, NBJ>(acc, InvS[0], lr, g);
+      if constexpr (SM::TINY) {
+        if (wact && wpos >= 2) trsm_regs_r<T, 0, NBI, NBJ>(acc, invr);
+      } else {
+        if (wact && wpos >= 2) trsm_regs<T, 0, NBI, NBJ>(acc, InvS[0], lr, g);
+      }
 
       if constexpr (SM::NSUB == 2) {
         if (two) {
@@ -789,7 +843,13 @@ static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_it
 }
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
                             const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp, int small_npad) {
+                            int32_t* status, const CoopPlan* cp, int small_npad, int tiny_npad) {
+  if (n_items > 0 && max_npad <= tiny_npad) {
+    if (cp && cp->n_blocks > 0) return hipErrorInvalidValue;  // cooperative ranks use 8-wave workgroups
+    hipLaunchKernelGGL((potrf::k_potrf<float, 128, false>), dim3(n_items), dim3(128), 0, L.stream, L.desc, order,
+                       L.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
+    return hipGetLastError();
+  }
   if (n_items > 0 && max_npad <= small_npad) {
     if (cp && cp->n_blocks > 0) return hipErrorInvalidValue;  // cooperative ranks use 8-wave workgroups
     hipLaunchKernelGGL((potrf::k_potrf<float, 256, false>), dim3(n_items), dim3(256), 0, L.stream, L.desc, order,

@@ -147,6 +147,27 @@ def test_ragged_sizes_and_degenerate_subsets(prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_ragged_sizes_up_to_512_points(prec, tol):
+    """Every subset pads to at most 512 rows, so the FP32 factorisation takes
+    its smallest shape (2-wave work-groups, 64-row chunks, the inverse tiles
+    of the triangular solves in registers): sizes around the 64-row tile,
+    n = 1, n = 0 with validation points and a skipped subset."""
+    sizes_T = [1, 2, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257, 400, 511, 512, 0, 37]
+    sizes_V = [3, 5, 7, 1, 9, 11, 13, 2, 4, 6, 30, 50, 4, 8, 10, 4, 0]
+    locs, y, tp, ti, vp, vi = _synthetic(sizes_T, sizes_V, 8)
+    say(f"[case] ragged up to 512 prec={prec} sizes={sizes_T}")
+    ref = oracle.cv_loss(locs, y, tp, ti, vp, vi, 0, 0.3, 0.1)
+    with pcv.Problem(locs, y, tp, ti, vp, vi, prec=prec) as P:
+        loss, rep = P.eval(pcv.theta(0.3, 0.1), report=True)
+    assert _rel(loss, ref["sspe"]) <= tol
+    check_sspe(rep["per_subset_sspe"], ref["per_subset_sspe"], prec, say)
+    act = ref["per_subset_nval"] > 0
+    check_logdet(rep["per_subset_logdet"][act], ref["per_subset_logdet"][act], np.array(sizes_T)[act], 0.1,
+                 prec, say)
+    assert rep["per_subset_sspe"][16] == 0.0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
 def test_subsets_above_4096_points(prec, tol):
     """Subsets of 5,000 and 4,097 training points take the solve variants
     for more than 4,096 padded rows; a small subset rides along."""
