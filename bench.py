@@ -72,7 +72,8 @@ def copy_probe(torch, mib):
     return gbs
 
 
-def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=True, log=print, warmup=0.0):
+def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=True, log=print, warmup=0.0,
+          window=None):
     """Kriging service on the factored problem: Poisson arrivals at `rate`
     requests/s for `seconds`, each with floor(10^U(0,4)) query locations
     uniform over the domain (gaps included), plus `n_opt` closed-loop
@@ -85,31 +86,34 @@ def serve(pcv, w, seconds, rate=200.0, n_opt=4, n_lhs=30, seed=11, with_evals=Tr
     P = pcv.Problem.from_workload(w, prec="mixed")
     P.factor(pcv.theta(th0, lam0, cov=w.cov))
     if warmup > 0:
-        out = _serve_run(pcv, w, P, warmup, rate, n_opt, n_lhs, r, with_evals, seed)
+        out = _serve_run(pcv, w, P, warmup, rate, n_opt, n_lhs, r, with_evals, seed, window)
         log(f"[serve] warm-up ({warmup} s) done: p50 {out['p50_ms']:.1f} ms")
-    out = _serve_run(pcv, w, P, seconds, rate, n_opt, n_lhs, r, with_evals, seed)
+    out = _serve_run(pcv, w, P, seconds, rate, n_opt, n_lhs, r, with_evals, seed, window)
     P.close()
     log(f"[serve] {'with' if with_evals else 'without'} evaluations: {out}")
     return out
 
 
-def _serve_run(pcv, w, P, seconds, rate, n_opt, n_lhs, r, with_evals, seed):
+def _serve_run(pcv, w, P, seconds, rate, n_opt, n_lhs, r, with_evals, seed, window=None):
     import threading
     import queue
     th0, lam0 = w.theta_true
     lo, hi = w.locs.min(0), w.locs.max(0)
-    srv = pcv.Server(P, max_inflight=256)
+    srv = pcv.Server(P, max_inflight=256, window=window)
     stop = threading.Event()
     evals = []
 
     def optimiser(k):
+        # walks its seeded Latin-hypercube design, again from the start when
+        # it is done, until the arrivals stop
         rr = np.random.default_rng(np.random.SeedSequence([1912, 13132, 5, seed, 100 + k]))
         u = (rr.permuted(np.tile(np.arange(n_lhs), (2, 1)), axis=1).T + rr.uniform(size=(n_lhs, 2))) / n_lhs
-        for a, b in u:
-            if stop.is_set():
-                return
-            t = pcv.theta(th0 * 4.0 ** (a - 0.5), lam0 * 4.0 ** (b - 0.5), cov=w.cov)
-            evals.append(srv.wait(srv.submit_eval(t)))
+        while True:
+            for a, b in u:
+                if stop.is_set():
+                    return
+                t = pcv.theta(th0 * 4.0 ** (a - 0.5), lam0 * 4.0 ** (b - 0.5), cov=w.cov)
+                evals.append(srv.wait(srv.submit_eval(t)))
 
     tickets = queue.Queue()
 
@@ -212,10 +216,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--workload", default="large", choices=["large", "plain", "batched", "uneven"])
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 5M workload (testing)")
-    ap.add_argument("--serve-warmup", type=float, default=0.0,
-                    help="seconds of the same traffic on a discarded server before each serving run")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of each serving run (0 = skip serving)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0,
+                    help="seconds of the same traffic on a discarded server before the serving run with "
+                         "optimisers (the kriging-only run warms up for at most 2 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the serving run with optimisers (0 = skip serving); the kriging-only "
+                         "run lasts at most 15 s")
+    ap.add_argument("--serve-window", type=float, default=None,
+                    help="kriging batching window while evaluations are active (s; library default 0.03)")
     ap.add_argument("--tune", action="store_true",
                     help="pick the launch shapes and schedule with pcv_autotune first (off by default: "
                          "the tuner is not yet cleared for GPU runs)")
@@ -426,8 +434,10 @@ def main():
         out["speedup_vs_fp64_path"] = s64 / s_per
     if a.serve_seconds > 0 and a.workload == "large":
         out["serving"] = {
-            "with_4_optimisers": serve(pcv, w, a.serve_seconds, log=log, warmup=a.serve_warmup),
-            "kriging_only": serve(pcv, w, a.serve_seconds, with_evals=False, log=log, warmup=a.serve_warmup),
+            "with_4_optimisers": serve(pcv, w, a.serve_seconds, log=log, warmup=a.serve_warmup,
+                                       window=a.serve_window),
+            "kriging_only": serve(pcv, w, min(a.serve_seconds, 15.0), with_evals=False, log=log,
+                                  warmup=min(a.serve_warmup, 2.0), window=a.serve_window),
         }
     if not a.no_cpu:
         cb, rel = cpu_baseline(w, (thetas[0].range, thetas[0].lambda_), rep["per_subset_sspe"],

@@ -433,6 +433,16 @@ pcv_status pcv_server_submit_predict(pcv_server* s, int64_t q, const double* qlo
 pcv_status pcv_server_submit_eval(pcv_server* s, const pcv_theta* theta, double* loss,
                                   pcv_ticket* ticket);
 
+/* Batching window for kriging while evaluations are active (default 0.03 s).
+ * Reading the resident factors dominates a kriging batch (a batch touching
+ * every subset reads all of them), so batches launched back to back would
+ * keep the device from the evaluations.  While evaluation requests are
+ * queued or running, a kriging batch is launched only once its oldest query
+ * has waited `seconds`, or the queue holds a full batch; with no evaluation
+ * active a batch is launched as soon as a workspace slot is free.  0 turns
+ * the window off.  Errors: PCV_ERR_INVALID (seconds outside [0, 10]). */
+pcv_status pcv_server_set_batch_window(pcv_server* s, double seconds);
+
 /* Wait for a request (timeout_s < 0: no limit) and collect it: returns the
  * request's own status, after which the ticket is no longer valid.
  * PCV_ERR_BUSY: not finished within timeout_s (the ticket stays valid).

@@ -461,6 +461,13 @@ pcv_status pcv_part_subsets(int64_t n, const double* locs, int32_t S, const doub
                            val_idx);
 }
 
+pcv_status pcv_server_set_batch_window(pcv_server* s, double seconds) {
+  pcv::g_err.clear();
+  if (!s) return fail(PCV_ERR_INVALID, "server is NULL");
+  if (!(seconds >= 0.0 && seconds <= 10.0)) return fail(PCV_ERR_INVALID, "window must be in [0, 10] seconds");
+  return pcv::server_set_window(s, seconds);
+}
+
 pcv_status pcv_server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight) {
   pcv::g_err.clear();
   if (!out) return fail(PCV_ERR_INVALID, "out is NULL");

@@ -225,6 +225,7 @@ pcv_status server_submit_predict(pcv_server* s, int64_t q, const double* ql, dou
                                  int32_t obs_noise, pcv_ticket* ticket);
 pcv_status server_submit_eval(pcv_server* s, const pcv_theta& th, double* loss, pcv_ticket* ticket);
 pcv_status server_wait(pcv_server* s, pcv_ticket t, double timeout_s);
+pcv_status server_set_window(pcv_server* s, double seconds);
 pcv_status server_report(pcv_server* s, pcv_server_report* out);
 pcv_status server_destroy(pcv_server* s);
 const pcv_problem* server_problem(const pcv_server* s);

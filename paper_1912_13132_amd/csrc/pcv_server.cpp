@@ -116,6 +116,14 @@ struct pcv_server {
   pcv_ticket next_id = 1;
   int32_t inflight = 0;
   bool stop = false;
+  // Batching window: while evaluations are queued or running, a kriging
+  // batch is launched only once its oldest query has waited window_s, or
+  // the queue holds a full slot, so that kriging leaves the device to the
+  // evaluations between batches; without evaluations a batch is launched
+  // as soon as a slot is free.
+  double window_s = 0.03;
+  int64_t queued_q = 0;   // queries queued and not yet in a batch
+  bool eval_busy = false; // the evaluator is running evaluations
 
   // statistics
   std::vector<double> lat_pred, lat_eval;
@@ -181,6 +189,7 @@ void take_batch_locked(pcv_server* s, Slot& sl) {
     if (j > r0) {
       sl.pieces.push_back(Piece{r, r0, j - r0, sl.nq});
       sl.nq += j - r0;
+      s->queued_q -= j - r0;
       sl.any_var |= (r->flag & KRIGE_VAR) != 0;
       r->next = j;
     }
@@ -199,10 +208,19 @@ void batcher(pcv_server* s) {
     int si;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      // drain the queue before stopping
-      s->cv_batch.wait(lk, [&] {
-        return (!s->pred_q.empty() && !s->free_slots.empty()) || (s->stop && s->pred_q.empty());
-      });
+      // drain the queue before stopping; while evaluations are active, wait
+      // for the window or a full slot
+      for (;;) {
+        if (s->stop && s->pred_q.empty()) break;
+        if (!s->pred_q.empty() && !s->free_slots.empty()) {
+          const bool evals = s->eval_busy || !s->eval_q.empty();
+          const double due = s->pred_q.front()->t_submit + s->window_s;
+          if (s->stop || !evals || s->queued_q >= s->q_cap || now_s() >= due) break;
+          s->cv_batch.wait_for(lk, std::chrono::duration<double>(std::max(0.0, due - now_s())));
+          continue;
+        }
+        s->cv_batch.wait(lk);
+      }
       if (s->pred_q.empty()) break;
       si = s->free_slots.front();
       s->free_slots.pop_front();
@@ -289,6 +307,7 @@ void completer(pcv_server* s) {
         r->failed = true;
         r->err = std::string("kriging batch: ") + hipGetErrorString(e);
         if (r->next < r->q) {
+          s->queued_q -= r->q - r->next;
           r->next = r->q = std::max(r->next, r->done);
           s->pred_q.erase(std::remove(s->pred_q.begin(), s->pred_q.end(), r), s->pred_q.end());
         }
@@ -319,6 +338,7 @@ void evaluator(pcv_server* s) {
         batch.push_back(s->eval_q.front());
         s->eval_q.pop_front();
       }
+      s->eval_busy = true;
     }
     th.resize(batch.size());
     loss.assign(batch.size(), 0.0);
@@ -337,8 +357,12 @@ void evaluator(pcv_server* s) {
     }
     for (size_t k = 0; k < batch.size(); ++k)
       if (sts[k] == PCV_OK) *batch[k]->loss = loss[k];
-    std::lock_guard<std::mutex> lk(s->mu);
-    for (size_t k = 0; k < batch.size(); ++k) finish_locked(s, batch[k], sts[k], errs[k]);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (size_t k = 0; k < batch.size(); ++k) finish_locked(s, batch[k], sts[k], errs[k]);
+      s->eval_busy = false;
+    }
+    s->cv_batch.notify_one();  // kriging need not wait for the window any more
   }
 }
 
@@ -480,6 +504,16 @@ pcv_status server_submit_predict(pcv_server* s, int64_t q, const double* ql, dou
     return PCV_OK;
   }
   s->pred_q.push_back(r);
+  s->queued_q += q;
+  s->cv_batch.notify_one();
+  return PCV_OK;
+}
+
+pcv_status server_set_window(pcv_server* s, double seconds) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->window_s = seconds;
+  }
   s->cv_batch.notify_one();
   return PCV_OK;
 }

@@ -127,6 +127,7 @@ def lib():
                                             ctypes.c_int32, _c_int64_p]
     L.pcv_server_submit_eval.argtypes = [P, ctypes.POINTER(Theta), _c_double_p, _c_int64_p]
     L.pcv_server_wait.argtypes = [P, ctypes.c_int64, ctypes.c_double]
+    L.pcv_server_set_batch_window.argtypes = [P, ctypes.c_double]
     L.pcv_server_stats.argtypes = [P, _c_double_p, _c_double_p, _c_double_p, _c_double_p]
     L.pcv_server_report_get.argtypes = [P, ctypes.POINTER(ServerReport)]
     L.pcv_server_destroy.argtypes = [P]
@@ -461,13 +462,19 @@ class Server:
     directly while the server exists.  Submit calls may come from several
     threads; they release the GIL while they block on admission."""
 
-    def __init__(self, problem, mem_budget=0, max_inflight=64):
+    def __init__(self, problem, mem_budget=0, max_inflight=64, window=None):
         self.problem = problem
         h = ctypes.c_void_p()
         _check(lib().pcv_server_create(ctypes.byref(h), problem._handle(), int(mem_budget),
                                        int(max_inflight)))
         self._h = h
         self._keep = {}
+        if window is not None:
+            st = lib().pcv_server_set_batch_window(h, float(window))
+            if st != 0:
+                err = PcvError(st, lib().pcv_last_error().decode())
+                self.close()
+                raise err
 
     def _handle(self):
         if self._h is None:

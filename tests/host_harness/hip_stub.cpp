@@ -469,7 +469,8 @@ static void launched(const char* what, std::function<void()> chk, hipStream_t s)
 }
 
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n, int, const float* cx, const float* cy,
-                            float* Lb, double* Inv, double* logdet, int32_t* status, const CoopPlan* cp, int) {
+                            float* Lb, double* Inv, double* logdet, int32_t* status, const CoopPlan* cp, int,
+                            int) {
   if (n <= 0) return hipSuccess;
   const CoopPlan c = cp ? *cp : CoopPlan{};
   launched("potrf_f32", [=] {

@@ -210,3 +210,32 @@ def test_wait_timeout_reports_busy_and_keeps_the_ticket(w_plain):
                 srv.wait(t)
     np.testing.assert_array_equal(m, alone[0])
     np.testing.assert_array_equal(v, alone[1])
+
+
+def test_batching_window_with_evaluations(w_plain):
+    """With a batching window and evaluations active, kriging batches wait
+    for the window (fewer, larger batches); every result still equals
+    pcv_predict alone bit for bit, and every loss equals pcv_eval.  A
+    window outside [0, 10] s is rejected."""
+    th = pcv.theta(0.1, 0.05)
+    reqs = _requests(w_plain, 20, 9)
+    ths = [pcv.theta(0.1 * (1 + 0.05 * k), 0.05) for k in range(4)]
+    say("[case] server batching window 0.05 s with evaluations")
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        direct = [P.eval(t) for t in ths]
+        P.factor(th)
+        alone = _alone(P, reqs, [False] * len(reqs))
+        with pytest.raises(pcv.PcvError) as e:
+            pcv.Server(P, window=-1.0)
+        assert e.value.status == 1
+        with pcv.Server(P, window=0.05) as srv:
+            te = [srv.submit_eval(t) for t in ths]
+            tp = [srv.submit_predict(q) for q in reqs]
+            preds = [srv.wait(t) for t in tp]
+            losses = [srv.wait(t) for t in te]
+            rep = srv.report()
+    assert losses == direct
+    for (m, v), (ma, va) in zip(preds, alone):
+        np.testing.assert_array_equal(m, ma)
+        np.testing.assert_array_equal(v, va)
+    say(f"   batches {rep['n_batches']} for {len(reqs)} requests")
