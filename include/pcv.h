@@ -79,8 +79,11 @@ typedef struct {
 
 typedef struct {
   int32_t prec;           /* pcv_prec; default PCV_PREC_MIXED                        */
-  int32_t max_refine;     /* mixed: refinement sweeps (default 1, max 8)             */
-  double refine_tol;      /* mixed: a subset whose residual before the last correction
+  int32_t max_refine;     /* mixed: refinement sweeps, at most (default 2, max 8).
+                             Every subset takes the first; a later one only where
+                             the residual the previous sweep measured has
+                             ||r||_2 > refine_tol * ||y_T||_2                    */
+  double refine_tol;      /* mixed: a subset whose residual before its last correction
                              has ||r||_2 > tol * ||y_T||_2 is re-run in FP64 (1e-4)  */
   void* hip_stream;       /* hipStream_t to run on; NULL = library-owned stream      */
   size_t mem_cap_bytes;   /* device workspace cap, 0 = no cap                         */
@@ -146,7 +149,8 @@ typedef struct {
   double ms_factor, ms_solve, ms_refine, ms_predict, ms_reduce;
   double* per_subset_sspe;   /* optional out [S]: z_i (0 for skipped subsets)       */
   double* per_subset_logdet; /* optional out [S]: log det(Sigma_i + lambda I)       */
-  int32_t* per_subset_iters; /* optional out [S]: refinement sweeps used            */
+  int32_t* per_subset_iters; /* optional out [S]: refinement sweeps used (0 for a
+                                subset re-run in FP64); pcv_eval only            */
   /* Composite likelihood over the evaluated subsets (Sec. 2.1, eq. (2) applied
    * to each subset's training data, tau = lambda sigma^2):
    *   -2 l_i = n_i log(2 pi) + n_i log sigma^2 + log det(Sigma_i + lambda I)

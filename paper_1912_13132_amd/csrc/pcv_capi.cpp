@@ -115,7 +115,7 @@ void pcv_default_options(pcv_options* opt) {
   if (!opt) return;
   std::memset(opt, 0, sizeof(*opt));
   opt->prec = PCV_PREC_MIXED;
-  opt->max_refine = 1;
+  opt->max_refine = 2;
   opt->refine_tol = 1e-4;
   opt->graph = 1;
 }

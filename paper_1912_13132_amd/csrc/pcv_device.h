@@ -109,24 +109,33 @@ hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, 
                             int32_t* status, const CoopPlan* cp = nullptr);
 // max_npad: the largest padded size among the launched subsets (selects the
 // per-thread register budget of the solve kernels).
+// gate (may be null): per descriptor, 0 = skip this subset (a refinement
+// sweep it does not take), see launch_refine_gate.
 hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const float* Lbuf, const double* Inv, const double* rhs_train,
-                               const double* rhs_pad, double* z, double* rhs2);
+                               const double* rhs_pad, double* z, double* rhs2, const int32_t* gate = nullptr);
 hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const double* Lbuf, const double* Inv, const double* rhs_train,
-                               const double* rhs_pad, double* z, double* rhs2);
+                               const double* rhs_pad, double* z, double* rhs2, const int32_t* gate = nullptr);
 hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const float* Lbuf, const double* Inv, const double* z, double* x,
-                               double* alpha_accum);
+                               double* alpha_accum, const int32_t* gate = nullptr);
 hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const double* Lbuf, const double* Inv, const double* z, double* x,
-                               double* alpha_accum);
+                               double* alpha_accum, const int32_t* gate = nullptr);
 // Refinement residual r = y_T - (Sigma + lambda I) alpha, each symmetric entry
 // generated once: tile items (subset, row block I) sorted by work, and row
 // items (subset, row block) for the fixed-order reduction.
 hipError_t launch_residual(const Launch& L, const int2* tile_items, int n_tile_items, const int2* row_items,
                            int n_row_items, const double* tx, const double* ty, const double* yT,
-                           const double* alpha, double* rrow, double* pcol, double* r);
+                           const double* alpha, double* rrow, double* pcol, double* r,
+                           const int32_t* gate = nullptr);
+// Before refinement sweep it >= 1, for the descriptors k = order[j], j < n:
+// gate[k] = 1 where descriptor k (subset k % S) took sweep it - 1 and that
+// sweep's squared residual norm rhs2[k] exceeds tol^2 ynorm2[k % S];
+// nsweep[k] = sweeps descriptor k takes.
+hipError_t launch_refine_gate(hipStream_t s, int n, const int32_t* order, int S, int it, const double* rhs2,
+                              const double* ynorm2, double tol, int32_t* gate, int32_t* nsweep);
 hipError_t launch_predict_val(const Launch& L, const int2* items, int n_items, const double* tx,
                               const double* ty, const double* vx, const double* vy,
                               const double* yV, const double* alpha, double* yhat, double* err);

@@ -50,6 +50,7 @@ struct pcv_batch {
   double *d_rrow = nullptr, *d_pcol = nullptr, *d_rhs2 = nullptr, *d_yhat = nullptr, *d_err = nullptr;
   double *d_logdet = nullptr, *d_sspe = nullptr, *d_quad = nullptr, *d_total = nullptr;
   int32_t *d_status = nullptr, *d_nbad = nullptr;
+  int32_t *d_gate = nullptr, *d_nsweep = nullptr;  // refinement sweeps taken, per descriptor
   pcv::ThetaDev* d_theta = nullptr;
   pcv::ThetaDev* h_theta = nullptr;  // pinned [B]
   double* h_total = nullptr;         // pinned [B]
@@ -147,6 +148,7 @@ struct pcv_problem {
   double *d_logdet = nullptr, *d_sspe = nullptr, *d_quad = nullptr;
   int32_t* d_status = nullptr;
   int32_t* d_bad = nullptr;         // subsets re-run in FP64
+  int32_t *d_gate = nullptr, *d_nsweep = nullptr;  // refinement sweeps taken, per subset
   // captured theta-evaluation: [0] as planned, [1] with one work-group per
   // subset (used while another shared launch is in flight on the device)
   hipGraphExec_t graph_exec[2] = {};

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
                                                      const double* __restrict__ rhs_train,
                                                      const double* __restrict__ rhs_pad,
                                                      double* __restrict__ zbuf,
-                                                     double* __restrict__ rhs2out) {
+                                                     double* __restrict__ rhs2out,
+                                                     const int32_t* __restrict__ gate) {
   typedef typename SVec<T>::type vec_t;
   constexpr int VW = SVec<T>::W;
   constexpr int LPR = TB / VW;           // lanes per row segment: 16 (FP32), 32 (FP64)
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
   __shared__ double tJ[64], zJ[64];
   __shared__ double b2s[SNT / 64];
   const int sidx = order[blockIdx.x];
+  if (gate && !gate[sidx]) return;  // a refinement sweep this subset does not take
   const SubsetDesc D = desc[sidx];
   const int n = D.n, npad = D.npad, nb = npad / TB;
   const T* __restrict__ L = Lbuf + D.offL;
@@ -268,11 +270,13 @@ __global__ __launch_bounds__(512, MQ <= 2 ? 4 : 2) void k_trsv_bwd(const SubsetD
                                                      const double* __restrict__ Invbuf,
                                                      const double* __restrict__ zbuf,
                                                      double* __restrict__ xbuf,
-                                                     double* __restrict__ alpha_accum) {
+                                                     double* __restrict__ alpha_accum,
+                                                     const int32_t* __restrict__ gate) {
   typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type q_t;
   __shared__ double IL[64][65];
   __shared__ double tJ[64], xJ[64];
   const int sidx = order[blockIdx.x];
+  if (gate && !gate[sidx]) return;
   const SubsetDesc D = desc[sidx];
   const int npad = D.npad, nb = npad / TB;
   const T* __restrict__ L = Lbuf + D.offL;
@@ -347,9 +351,11 @@ __global__ __launch_bounds__(256, 3) void k_residual_tiles(const SubsetDesc* __r
                                                         const double* __restrict__ ty,
                                                         const double* __restrict__ alphabuf,
                                                         double* __restrict__ rrow,
-                                                        double* __restrict__ pcol) {
+                                                        double* __restrict__ pcol,
+                                                        const int32_t* __restrict__ gate) {
   __shared__ double red[4][64];
   const int2 it = items[blockIdx.x];
+  if (gate && !gate[it.x]) return;
   const SubsetDesc D = desc[it.x];
   const int I = it.y, n = D.n;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -445,8 +451,10 @@ __global__ __launch_bounds__(64) void k_residual_reduce(const SubsetDesc* __rest
                                                         const double* __restrict__ alphabuf,
                                                         const double* __restrict__ rrow,
                                                         const double* __restrict__ pcol,
-                                                        double* __restrict__ rbuf) {
+                                                        double* __restrict__ rbuf,
+                                                        const int32_t* __restrict__ gate) {
   const int2 it = items[blockIdx.x];
+  if (gate && !gate[it.x]) return;
   const SubsetDesc D = desc[it.x];
   const int J = it.y, n = D.n, nb = D.npad / TB;
   const int row = 64 * J + threadIdx.x;
@@ -709,61 +717,89 @@ __global__ __launch_bounds__(256) void k_gls(const SubsetDesc* __restrict__ desc
 template <typename T>
 static hipError_t fwd_launch(const Launch& Lc, const int32_t* order, int n_items, int max_npad, const T* Lbuf,
                              const double* Inv, const double* rt, const double* rp, double* z,
-                             double* rhs2) {
+                             double* rhs2, const int32_t* gate) {
   if (n_items <= 0) return hipSuccess;
   // slots per thread = npad / 512 at most; the 32-slot variant (subsets above
   // 8,192 padded rows) spills part of its registers
   if (max_npad <= 4096)
     hipLaunchKernelGGL((k_trsv_fwd<T, 8>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                       rt, rp, z, rhs2);
+                       rt, rp, z, rhs2, gate);
   else if (max_npad <= 8192)
     hipLaunchKernelGGL((k_trsv_fwd<T, 16>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                       rt, rp, z, rhs2);
+                       rt, rp, z, rhs2, gate);
   else
     hipLaunchKernelGGL((k_trsv_fwd<T, 32>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                       rt, rp, z, rhs2);
+                       rt, rp, z, rhs2, gate);
   return hipGetLastError();
 }
 hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const float* Lbuf, const double* Inv, const double* rt, const double* rp,
-                               double* z, double* rhs2) {
-  return fwd_launch<float>(L, order, n_items, max_npad, Lbuf, Inv, rt, rp, z, rhs2);
+                               double* z, double* rhs2, const int32_t* gate) {
+  return fwd_launch<float>(L, order, n_items, max_npad, Lbuf, Inv, rt, rp, z, rhs2, gate);
 }
 hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
                                const double* Lbuf, const double* Inv, const double* rt, const double* rp,
-                               double* z, double* rhs2) {
-  return fwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, rt, rp, z, rhs2);
+                               double* z, double* rhs2, const int32_t* gate) {
+  return fwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, rt, rp, z, rhs2, gate);
 }
 
 template <typename T>
 static hipError_t bwd_launch(const Launch& Lc, const int32_t* order, int n_items, int max_npad, const T* Lbuf,
-                             const double* Inv, const double* z, double* x, double* acc) {
+                             const double* Inv, const double* z, double* x, double* acc, const int32_t* gate) {
   if (n_items <= 0) return hipSuccess;
   if (max_npad <= 4096)
     hipLaunchKernelGGL((k_trsv_bwd<T, 2>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                       z, x, acc);
+                       z, x, acc, gate);
   else
     hipLaunchKernelGGL((k_trsv_bwd<T, 8>), dim3(n_items), dim3(SNT), 0, Lc.stream, Lc.desc, order, Lbuf, Inv,
-                       z, x, acc);
+                       z, x, acc, gate);
   return hipGetLastError();
 }
 hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* order, int n_items, int max_npad,
-                               const float* Lbuf, const double* Inv, const double* z, double* x, double* acc) {
-  return bwd_launch<float>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc);
+                               const float* Lbuf, const double* Inv, const double* z, double* x, double* acc,
+                               const int32_t* gate) {
+  return bwd_launch<float>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc, gate);
 }
 hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* order, int n_items, int max_npad,
-                               const double* Lbuf, const double* Inv, const double* z, double* x, double* acc) {
-  return bwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc);
+                               const double* Lbuf, const double* Inv, const double* z, double* x, double* acc,
+                               const int32_t* gate) {
+  return bwd_launch<double>(L, order, n_items, max_npad, Lbuf, Inv, z, x, acc, gate);
 }
 
 hipError_t launch_residual(const Launch& Lc, const int2* tile_items, int n_tile_items, const int2* row_items,
                            int n_row_items, const double* tx, const double* ty, const double* yT,
-                           const double* alpha, double* rrow, double* pcol, double* r) {
+                           const double* alpha, double* rrow, double* pcol, double* r, const int32_t* gate) {
   if (n_tile_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_residual_tiles, dim3(n_tile_items), dim3(256), 0, Lc.stream, Lc.desc, tile_items,
-                     Lc.theta, tx, ty, alpha, rrow, pcol);
+                     Lc.theta, tx, ty, alpha, rrow, pcol, gate);
   hipLaunchKernelGGL(k_residual_reduce, dim3(n_row_items), dim3(64), 0, Lc.stream, Lc.desc, row_items,
-                     Lc.theta, yT, alpha, rrow, pcol, r);
+                     Lc.theta, yT, alpha, rrow, pcol, r, gate);
+  return hipGetLastError();
+}
+
+// Before sweep it >= 1 of the refinement, for the descriptors k = order[j],
+// j < n: a subset takes the sweep only if it took sweep it - 1 and the
+// residual that sweep measured, ||r||^2 = rhs2[k], is above tol^2 ||y_T||^2
+// (gate[k] = 1, else 0); nsweep[k] counts the sweeps it takes (set at it = 1,
+// so nothing needs clearing).  Descriptor k belongs to subset k % S.
+__global__ __launch_bounds__(256) void k_refine_gate(int n, const int32_t* __restrict__ order, int S, int it,
+                                                     const double* __restrict__ rhs2,
+                                                     const double* __restrict__ ynorm2, double tol2,
+                                                     int32_t* __restrict__ gate, int32_t* __restrict__ nsweep) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int k = order[j];
+  const int32_t done = it == 1 ? 1 : nsweep[k];
+  const bool take = done == it && rhs2[k] > tol2 * ynorm2[k % S];
+  gate[k] = take ? 1 : 0;
+  nsweep[k] = take ? it + 1 : done;
+}
+
+hipError_t launch_refine_gate(hipStream_t s, int n, const int32_t* order, int S, int it, const double* rhs2,
+                              const double* ynorm2, double tol, int32_t* gate, int32_t* nsweep) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_gate, dim3((n + 255) / 256), dim3(256), 0, s, n, order, S, it, rhs2, ynorm2,
+                     tol * tol, gate, nsweep);
   return hipGetLastError();
 }
 

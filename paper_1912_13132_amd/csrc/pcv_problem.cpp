@@ -487,6 +487,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(dalloc(p, &p->d_quad, (size_t)S));
   TRY(dalloc(p, &p->d_status, (size_t)S));
   TRY(dalloc(p, &p->d_bad, (size_t)S));
+  TRY(dalloc(p, &p->d_gate, (size_t)S));
+  TRY(dalloc(p, &p->d_nsweep, (size_t)S));
   TRY(dalloc(p, &p->d_theta, 1));
   TRY(dalloc(p, &p->d_total, 1));
   TRY(dalloc(p, &p->d_nbad, 1));
@@ -758,15 +760,23 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
       }
       break;
     case 3:
+      // every subset takes the first sweep; a later one only where the
+      // residual the previous sweep measured is still above refine_tol
       for (int it = 0; it < sweeps; ++it) {
+        const int32_t* gate = it > 0 ? p->d_gate : nullptr;
+        if (it > 0) {
+          HIPCHK(launch_refine_gate(st, cnt, order, p->S, it, p->d_rhs2, p->d_ynorm2, p->opt.refine_tol,
+                                    p->d_gate, p->d_nsweep));
+          PACE();
+        }
         HIPCHK(launch_residual(Lc, p->d_tile_items + G.r0, G.nr, p->d_row_items + G.r0, G.nr, p->d_tx, p->d_ty,
-                               p->d_yT, p->d_alpha, p->d_rrow, p->d_pcol, p->d_r));
+                               p->d_yT, p->d_alpha, p->d_rrow, p->d_pcol, p->d_r, gate));
         PACE();
         HIPCHK(launch_trsv_fwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, nullptr,
-                                   p->d_r, p->d_z, p->d_rhs2));
+                                   p->d_r, p->d_z, p->d_rhs2, gate));
         PACE();
         HIPCHK(launch_trsv_bwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
-                                   p->d_x, p->d_alpha));
+                                   p->d_x, p->d_alpha, gate));
         PACE();
       }
       break;
@@ -947,6 +957,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
   Launch Lc{p->stream, p->d_desc, p->d_theta};
 
   int32_t n_fallback = 0;
+  std::vector<int32_t> fb_list;
   const bool force_fb = mixed && (p->opt.debug_flags & 1) && p->n_active > 0;
   if (*p->h_nbad > 0 || force_fb) {
     std::vector<int32_t> status(p->S);
@@ -963,6 +974,7 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     }
     // FP64 re-run of the subsets whose FP32 factorisation broke down
     n_fallback = (int32_t)bad.size();
+    fb_list = bad;
     s = ensure_L(p, true);
     if (s != PCV_OK) return s;
     int32_t* d_bad = p->d_bad;
@@ -994,7 +1006,20 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     rep->mse = p->n_val_total ? *loss / (double)p->n_val_total : 0.0;
     rep->n_subsets_used = p->n_active;
     rep->n_fallback_fp64 = n_fallback;
-    rep->max_refine_iters = sweeps;
+    // sweeps per subset: all of them with one sweep or none, else as the
+    // gates decided; a subset re-run in FP64 counts none
+    std::vector<int32_t> ns(p->S, 0);
+    if (sweeps > 1) HIPCHK(hipMemcpy(ns.data(), p->d_nsweep, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost));
+    std::vector<char> fb(p->S, 0);
+    for (int32_t i : fb_list) fb[i] = 1;
+    rep->max_refine_iters = 0;
+    for (int32_t i : p->order_eval) {
+      if (sweeps <= 1) ns[i] = sweeps;
+      if (fb[i]) ns[i] = 0;
+      rep->max_refine_iters = std::max(rep->max_refine_iters, ns[i]);
+    }
+    if (rep->per_subset_iters)
+      for (int32_t i = 0; i < p->S; ++i) rep->per_subset_iters[i] = p->active[i] ? ns[i] : 0;
     rep->max_rel_residual = 0.0;
     if (sweeps > 0) {
       std::vector<double> r2(p->S);
@@ -1009,8 +1034,6 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
       HIPCHK(hipMemcpy(ld.data(), p->d_logdet, sizeof(double) * p->S, hipMemcpyDeviceToHost));
       for (int32_t i = 0; i < p->S; ++i) rep->per_subset_logdet[i] = p->active[i] ? ld[i] : 0.0;
     }
-    if (rep->per_subset_iters)
-      for (int32_t i = 0; i < p->S; ++i) rep->per_subset_iters[i] = p->active[i] ? sweeps : 0;
     {
       // composite likelihood, summed in subset order with compensation
       std::vector<double> ld(p->S), qd(p->S);
@@ -1060,7 +1083,7 @@ namespace {
 // Device bytes of one theta slot of the batch workspace.
 size_t batch_slot_bytes(const pcv_problem* p, bool mixed) {
   return (size_t)p->nL * (mixed ? 4 : 8) + (size_t)p->nInv * 8 + (size_t)p->nP * 8 * 6 +
-         (size_t)p->nPC * 8 + (size_t)p->nnzV * 8 * 2 + (size_t)p->S * (8 * 4 + 4 + sizeof(SubsetDesc)) + 64;
+         (size_t)p->nPC * 8 + (size_t)p->nnzV * 8 * 2 + (size_t)p->S * (8 * 4 + 4 * 3 + sizeof(SubsetDesc)) + 64;
 }
 
 pcv_status ensure_batch(pcv_problem* p, int B, bool mixed) {
@@ -1103,6 +1126,8 @@ pcv_status ensure_batch(pcv_problem* p, int B, bool mixed) {
   TRYB(dalloc(p, &b.d_err, (size_t)B * std::max<int64_t>(p->nnzV, 1)));
   for (double** q : {&b.d_rhs2, &b.d_logdet, &b.d_sspe, &b.d_quad}) TRYB(dalloc(p, q, (size_t)B * S));
   TRYB(dalloc(p, &b.d_status, (size_t)B * S));
+  TRYB(dalloc(p, &b.d_gate, (size_t)B * S));
+  TRYB(dalloc(p, &b.d_nsweep, (size_t)B * S));
   TRYB(dalloc(p, &b.d_total, (size_t)B));
   TRYB(dalloc(p, &b.d_nbad, (size_t)B));
   TRYB(dalloc(p, &b.d_theta, (size_t)B));
@@ -1200,13 +1225,20 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
     HIPCHK(pace());
     if (ev) HIPCHK(hipEventRecord(p->ev[2], st));
     for (int it = 0; it < sweeps; ++it) {
+      const int32_t* gate = it > 0 ? b.d_gate : nullptr;
+      if (it > 0) {
+        HIPCHK(launch_refine_gate(st, pl.n_order, pl.d_order, p->S, it, b.d_rhs2, p->d_ynorm2, p->opt.refine_tol,
+                                  b.d_gate, b.d_nsweep));
+        HIPCHK(pace());
+      }
       HIPCHK(launch_residual(Lc, pl.d_tile_items, pl.n_tile, pl.d_row_items, pl.n_row, p->d_tx, p->d_ty, p->d_yT,
-                             b.d_alpha, b.d_rrow, b.d_pcol, b.d_r));
+                             b.d_alpha, b.d_rrow, b.d_pcol, b.d_r, gate));
       HIPCHK(pace());
       HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, nullptr, b.d_r, b.d_z,
-                                 b.d_rhs2));
+                                 b.d_rhs2, gate));
       HIPCHK(pace());
-      HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_x, b.d_alpha));
+      HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_x, b.d_alpha,
+                                 gate));
       HIPCHK(pace());
     }
   } else {

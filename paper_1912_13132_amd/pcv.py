@@ -257,7 +257,7 @@ class Problem:
     steps 2-5: divide and read once, evaluate many zeta)."""
 
     def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
-                 prec="mixed", max_refine=1, refine_tol=1e-4, stream=None, mem_cap=0,
+                 prec="mixed", max_refine=2, refine_tol=1e-4, stream=None, mem_cap=0,
                  profile=False, debug_flags=0, graph=True, max_wg_per_subset=0):
         """Arrays are numpy-like (host) or, when locs is a torch tensor on the
         GPU, torch tensors on that device (the library's inputs_on_device

@@ -501,41 +501,53 @@ hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n, const 
 }
 template <typename T>
 static hipError_t trsv(const char* what, const Launch& L, const int32_t* order, int n, const T* Lb,
-                       const double* Inv, const void* a, const void* b, const void* c, const void* d) {
+                       const double* Inv, const void* a, const void* b, const void* c, const void* d,
+                       const int32_t* gate) {
   if (n <= 0) return hipSuccess;
   launched(what, [=] {
     dev_ptr(L.desc, what); dev_ptr(L.theta, what); dev_range(order, 4 * (size_t)n, what);
     dev_ptr(Lb, what); dev_ptr(Inv, what); dev_ptr(a, what); dev_ptr(b, what); dev_ptr(c, what); dev_ptr(d, what);
+    dev_ptr(gate, what);
   }, L.stream);
   return hipSuccess;
 }
 hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* o, int n, int, const float* Lb, const double* Inv,
-                               const double* rt, const double* rp, double* z, double* r2) {
-  return trsv("trsv_fwd_f32", L, o, n, Lb, Inv, rt, rp, z, r2);
+                               const double* rt, const double* rp, double* z, double* r2, const int32_t* g) {
+  return trsv("trsv_fwd_f32", L, o, n, Lb, Inv, rt, rp, z, r2, g);
 }
 hipError_t launch_trsv_fwd_f64(const Launch& L, const int32_t* o, int n, int, const double* Lb, const double* Inv,
-                               const double* rt, const double* rp, double* z, double* r2) {
-  return trsv("trsv_fwd_f64", L, o, n, Lb, Inv, rt, rp, z, r2);
+                               const double* rt, const double* rp, double* z, double* r2, const int32_t* g) {
+  return trsv("trsv_fwd_f64", L, o, n, Lb, Inv, rt, rp, z, r2, g);
 }
 hipError_t launch_trsv_bwd_f32(const Launch& L, const int32_t* o, int n, int, const float* Lb, const double* Inv,
-                               const double* z, double* x, double* acc) {
-  return trsv("trsv_bwd_f32", L, o, n, Lb, Inv, z, x, acc, nullptr);
+                               const double* z, double* x, double* acc, const int32_t* g) {
+  return trsv("trsv_bwd_f32", L, o, n, Lb, Inv, z, x, acc, nullptr, g);
 }
 hipError_t launch_trsv_bwd_f64(const Launch& L, const int32_t* o, int n, int, const double* Lb, const double* Inv,
-                               const double* z, double* x, double* acc) {
-  return trsv("trsv_bwd_f64", L, o, n, Lb, Inv, z, x, acc, nullptr);
+                               const double* z, double* x, double* acc, const int32_t* g) {
+  return trsv("trsv_bwd_f64", L, o, n, Lb, Inv, z, x, acc, nullptr, g);
 }
 hipError_t launch_residual(const Launch& L, const int2* ti, int nt, const int2* ri, int nr, const double* tx,
                            const double* ty, const double* yT, const double* alpha, double* rrow, double* pcol,
-                           double* r) {
+                           double* r, const int32_t* gate) {
   if (nt <= 0 && nr <= 0) return hipSuccess;
   launched("residual", [=] {
     if (nt > 0) dev_range(ti, 8 * (size_t)nt, "residual tile items");
     if (nr > 0) dev_range(ri, 8 * (size_t)nr, "residual row items");
     for (const void* p : {(const void*)tx, (const void*)ty, (const void*)yT, (const void*)alpha, (const void*)rrow,
-                          (const void*)pcol, (const void*)r})
+                          (const void*)pcol, (const void*)r, (const void*)gate})
       dev_ptr(p, "residual");
   }, L.stream);
+  return hipSuccess;
+}
+hipError_t launch_refine_gate(hipStream_t s, int n, const int32_t* order, int, int, const double* rhs2,
+                              const double* ynorm2, double, int32_t* gate, int32_t* nsweep) {
+  if (n <= 0) return hipSuccess;
+  launched("refine_gate", [=] {
+    dev_range(order, 4 * (size_t)n, "refine_gate order");
+    for (const void* p : {(const void*)rhs2, (const void*)ynorm2, (const void*)gate, (const void*)nsweep})
+      dev_ptr(p, "refine_gate");
+  }, s);
   return hipSuccess;
 }
 hipError_t launch_predict_val(const Launch& L, const int2* items, int n, const double* tx, const double* ty,

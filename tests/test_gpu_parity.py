@@ -46,7 +46,7 @@ def _rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
-def _check_full(w, th, prec, tol, max_refine=1):
+def _check_full(w, th, prec, tol, max_refine=2):
     say(f"[case] {w.name} N={len(w.y)} S={w.part.n_subsets} prec={prec} "
         f"theta=({th.range},{th.lambda_},cov={th.cov})")
     ref = _oracle(w, th)
@@ -253,6 +253,67 @@ def test_refinement_convergence_test_falls_back(w_plain):
         loss, rep = P.eval(th, report=True)
     assert rep["n_fallback_fp64"] == 0
     assert 0.0 < rep["max_rel_residual"] <= 1e-4
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_second_sweep_only_where_residual_above_tol(w_batched_small, graph):
+    """A second refinement sweep runs only for the subsets whose first-sweep
+    residual exceeds refine_tol.  With refine_tol just below the largest
+    first-sweep residual the subset that has it takes two sweeps and the
+    others (residuals of distinct subsets differ) one; none
+    falls back (the second sweep's residual is far below the threshold), the
+    one-sweep subsets keep the one-sweep result bit for bit, every subset's
+    SSPE is within the mixed tolerance of the oracle, and pcv_eval_batch
+    gates the same way (bit-identical losses)."""
+    w = w_batched_small
+    th = pcv.theta(*w.theta_true)
+    say(f"[case] gated second sweep graph={graph}")
+    ref = _oracle(w, th)
+    with pcv.Problem.from_workload(w, prec="mixed", max_refine=1, refine_tol=1.0, graph=graph) as P:
+        l1, r1 = P.eval(th, report=True)
+    m1 = r1["max_rel_residual"]
+    assert 0.0 < m1 <= 1e-4 and r1["n_fallback_fp64"] == 0
+    act = ref["per_subset_nval"] > 0
+    assert np.all(r1["per_subset_iters"][act] == 1)
+    with pcv.Problem.from_workload(w, prec="mixed", max_refine=2, refine_tol=m1 * (1 - 1e-9), graph=graph) as P:
+        l2, r2 = P.eval(th, report=True)
+        g = W.theta_grid(w.theta_true, 2)
+        ths = [th] + [pcv.theta(*t) for t in g]
+        single = [P.eval(t) for t in ths]
+        batch = P.eval_batch(ths)
+    it = r2["per_subset_iters"]
+    say(f"   max first-sweep residual {m1:.2e}: {int((it[act] == 2).sum())} of {int(act.sum())} subsets "
+        f"took a second sweep; max residual corrected last {r2['max_rel_residual']:.2e}")
+    assert r2["n_fallback_fp64"] == 0 and r2["max_refine_iters"] == 2
+    assert set(np.unique(it[act])) == {1, 2}
+    assert np.all(it[~act] == 0)
+    one = act & (it == 1)
+    np.testing.assert_array_equal(r2["per_subset_sspe"][one], r1["per_subset_sspe"][one])
+    assert _rel(l2, ref["sspe"]) <= TOL_MIXED
+    check_sspe(r2["per_subset_sspe"], ref["per_subset_sspe"], "mixed", say)
+    assert single[0] == l2
+    np.testing.assert_array_equal(batch, single)
+
+
+@pytest.mark.parametrize("lam", [1e-3, 3e-4])
+def test_small_nugget_second_sweep_avoids_fallback(w_plain, lam):
+    """Small nugget: the FP32 factor is poorly conditioned, so a subset's
+    first-sweep residual can exceed refine_tol.  The default two sweeps
+    re-run in FP64 no more subsets than one sweep does, and the loss stays
+    within the mixed tolerance of the oracle."""
+    th = pcv.theta(0.3, lam)
+    say(f"[case] small nugget lambda={lam}")
+    ref = _oracle(w_plain, th)
+    out = {}
+    for mr in (1, 2):
+        with pcv.Problem.from_workload(w_plain, prec="mixed", max_refine=mr) as P:
+            loss, rep = P.eval(th, report=True)
+        out[mr] = rep["n_fallback_fp64"]
+        say(f"   max_refine={mr}: fallback {rep['n_fallback_fp64']} max rel residual "
+            f"{rep['max_rel_residual']:.2e} loss rel err {_rel(loss, ref['sspe']):.2e}")
+        assert _rel(loss, ref["sspe"]) <= TOL_MIXED
+        check_sspe(rep["per_subset_sspe"], ref["per_subset_sspe"], "mixed", say)
+    assert out[2] <= out[1]
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
