@@ -211,7 +211,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--max-refine", type=int, default=1)
+    ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--workload", default="large", choices=["large", "plain", "batched", "uneven"])
@@ -331,7 +331,8 @@ def main():
             f"loss {losses[0]:.12g}")
         P.close()
         # phase times and the factorisation launch's time: eager launches with events
-        Pp = pcv.Problem.from_workload(w, prec=prec, max_refine=a.max_refine, stream=stream, profile=True)
+        Pp = pcv.Problem.from_workload(w, prec=prec, max_refine=a.max_refine, stream=stream, profile=True,
+                                       est_error=True)
         if a.tune:
             Pp.autotune(thetas[0], cache=tune_cache, reps=3)  # the same choice, from the cache
         facs, facs_all = [], []
@@ -351,6 +352,7 @@ def main():
             _, r1 = Pp.eval(thetas[0], report=True)
             reps[0]["per_subset_sspe"] = r1["per_subset_sspe"]
             reps[0]["max_rel_residual"] = r1["max_rel_residual"]
+            reps[0]["est_rel_err"] = r1["est_rel_err"]
         Pp.close()
         return (losses, reps, total / (steps * len(thetas)), float(np.mean(facs)), float(np.mean(facs_all)),
                 tune)
@@ -422,6 +424,9 @@ def main():
     out["phase_ms"] = {k: rep[k] for k in ("ms_factor", "ms_solve", "ms_refine", "ms_predict", "ms_reduce")}
     out["max_rel_residual"] = max(r["max_rel_residual"] for r in reps)
     out["n_fallback_fp64"] = sum(r["n_fallback_fp64"] for r in reps)
+    # the library's own estimate of the loss error against the FP64 path
+    # (one more refinement sweep on a copy), beside the measured difference
+    out["est_rel_err"] = reps[0]["est_rel_err"]
     if a.prec == "mixed" and not a.no_fp64:
         losses64, reps64, s64, ms64, ms64_all, tune64 = run("fp64", max(2, a.steps // 2), 1)
         n64 = int(reps64[0]["n_factor_first"])

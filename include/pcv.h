@@ -130,7 +130,17 @@ typedef struct {
                              FP64 (mixed) or the evaluation fails with
                              PCV_ERR_DEVICE (FP64): set 1 when several
                              processes evaluate on one device */
-  int32_t reserved[3];
+  int32_t est_error;      /* mixed, nonzero: pcv_eval estimates its loss error
+                             against the FP64 path (est_rel_err of the report):
+                             one more refinement sweep is applied to a copy of
+                             every FP32-factored subset's alpha and the loss
+                             recomputed from it; the refinement contracts the
+                             solve error by a large factor per sweep, so the
+                             loss change is the current loss error up to that
+                             factor.  Costs about one sweep and one
+                             prediction pass per pcv_eval that asks for a
+                             report.  Default 0 */
+  int32_t reserved[2];
 } pcv_options;
 
 /* Per-evaluation report.  Arrays are optional, caller-owned, length S. */
@@ -172,6 +182,10 @@ typedef struct {
   int32_t n_factor_first;
   int32_t n_coop_subsets;
   double ms_factor_all;
+  /* pcv_eval's estimated relative error of the loss against the FP64 path:
+   * |loss - loss'| / |loss|, loss' the loss after one more refinement sweep
+   * (see est_error).  0 in FP64 mode, -1 when not estimated. */
+  double est_rel_err;
 } pcv_eval_report;
 
 typedef struct pcv_problem pcv_problem;

@@ -149,6 +149,10 @@ struct pcv_problem {
   int32_t* d_status = nullptr;
   int32_t* d_bad = nullptr;         // subsets re-run in FP64
   int32_t *d_gate = nullptr, *d_nsweep = nullptr;  // refinement sweeps taken, per subset
+  // error estimate (opt.est_error): predictions, squared errors, per-subset
+  // SSPE and total from alpha after one more sweep; allocated on first use
+  double *d_est_yhat = nullptr, *d_est_err = nullptr, *d_est_sspe = nullptr, *d_est_total = nullptr;
+  int32_t* d_est_nbad = nullptr;
   // captured theta-evaluation: [0] as planned, [1] with one work-group per
   // subset (used while another shared launch is in flight on the device)
   hipGraphExec_t graph_exec[2] = {};

@@ -938,6 +938,47 @@ pcv_status enqueue_eval(pcv_problem* p, bool mixed, int sweeps) {
   return PCV_OK;
 }
 
+// Error estimate of a mixed evaluation (opt.est_error): one more refinement
+// sweep over the subsets in fp_list's complement that were factored in FP32,
+// its correction added to a copy of alpha (d_rrow, free once the residual is
+// formed), and the loss recomputed from the copy into est_total.  The
+// evaluation's own buffers other than d_r, d_z, d_x, d_rrow, d_pcol and
+// d_gate are left as they are.
+pcv_status estimate_loss(pcv_problem* p, const std::vector<int32_t>& fb_list, double* out_total) {
+  pcv_status s;
+  if (!p->d_est_yhat) {
+    const size_t nv = (size_t)std::max<int64_t>(p->nnzV, 1);
+    if ((s = dalloc(p, &p->d_est_yhat, nv)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_est_err, nv)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_est_sspe, (size_t)p->S)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_est_total, 1)) != PCV_OK) return s;
+    if ((s = dalloc(p, &p->d_est_nbad, 1)) != PCV_OK) return s;
+  }
+  hipStream_t st = p->stream;
+  Launch Lc{st, p->d_desc, p->d_theta};
+  std::vector<int32_t> gate(p->S, 0);
+  for (int32_t i : p->order_eval) gate[i] = 1;
+  for (int32_t i : fb_list) gate[i] = 0;
+  HIPCHK(hipMemcpyAsync(p->d_gate, gate.data(), sizeof(int32_t) * p->S, hipMemcpyHostToDevice, st));
+  const pcv_group& G = p->g_all;
+  const int32_t* order = p->d_order_eval;
+  const int cnt = p->n_active;
+  HIPCHK(launch_residual(Lc, p->d_tile_items + G.r0, G.nr, p->d_row_items + G.r0, G.nr, p->d_tx, p->d_ty, p->d_yT,
+                         p->d_alpha, p->d_rrow, p->d_pcol, p->d_r, p->d_gate));
+  HIPCHK(hipMemcpyAsync(p->d_rrow, p->d_alpha, sizeof(double) * p->nP, hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_trsv_fwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, nullptr, p->d_r, p->d_z, nullptr,
+                             p->d_gate));
+  HIPCHK(launch_trsv_bwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_z, p->d_x, p->d_rrow,
+                             p->d_gate));
+  HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx, p->d_vy,
+                            p->d_yV, p->d_rrow, p->d_est_yhat, p->d_est_err));
+  HIPCHK(launch_reduce(st, p->d_desc, p->S, 1, p->d_est_err, p->d_status, p->d_active, nullptr, nullptr, 0.0,
+                       p->d_est_sspe, p->d_est_total, p->d_est_nbad));
+  HIPCHK(hipMemcpyAsync(out_total, p->d_est_total, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return PCV_OK;
+}
+
 }  // namespace
 
 pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval_report* rep) {
@@ -1000,7 +1041,17 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
     }
   }
   *loss = *p->h_total;
+  double est = mixed ? -1.0 : 0.0;
+  // (only when a report asks for it)
+  if (rep && mixed && p->opt.est_error && p->n_active > 0 && (int32_t)fb_list.size() < p->n_active) {
+    double total2 = 0.0;
+    if ((s = estimate_loss(p, fb_list, &total2)) != PCV_OK) return s;
+    est = *loss != 0.0 ? std::fabs(*loss - total2) / std::fabs(*loss) : std::fabs(total2);
+  } else if (mixed && p->opt.est_error) {
+    est = 0.0;  // every evaluated subset came from the FP64 path
+  }
   if (rep) {
+    rep->est_rel_err = est;
     rep->sspe = *loss;
     rep->n_val = p->n_val_total;
     rep->mse = p->n_val_total ? *loss / (double)p->n_val_total : 0.0;
@@ -1282,6 +1333,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
     rep->n_fallback_fp64 = 0;
     rep->n_val = p->n_val_total;
     rep->n_subsets_used = p->n_active;
+    rep->est_rel_err = p->opt.prec == PCV_PREC_MIXED ? -1.0 : 0.0;
   }
   const bool mixed = p->opt.prec == PCV_PREC_MIXED;
   const int sweeps = mixed ? p->opt.max_refine : 0;

@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
                 ("mem_cap_bytes", ctypes.c_size_t), ("profile", ctypes.c_int32),
                 ("debug_flags", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("inputs_on_device", ctypes.c_int32), ("max_wg_per_subset", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("est_error", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class EvalReport(ctypes.Structure):
@@ -66,7 +66,8 @@ class EvalReport(ctypes.Structure):
                 ("per_subset_sspe", _c_double_p), ("per_subset_logdet", _c_double_p),
                 ("per_subset_iters", _c_int32_p), ("neg2loglik", ctypes.c_double),
                 ("per_subset_neg2loglik", _c_double_p), ("n_factor_first", ctypes.c_int32),
-                ("n_coop_subsets", ctypes.c_int32), ("ms_factor_all", ctypes.c_double)]
+                ("n_coop_subsets", ctypes.c_int32), ("ms_factor_all", ctypes.c_double),
+                ("est_rel_err", ctypes.c_double)]
 
 
 class ServerReport(ctypes.Structure):
@@ -258,7 +259,7 @@ class Problem:
 
     def __init__(self, locs, y, train_ptr, train_idx, val_ptr, val_idx, core_rect=None,
                  prec="mixed", max_refine=2, refine_tol=1e-4, stream=None, mem_cap=0,
-                 profile=False, debug_flags=0, graph=True, max_wg_per_subset=0):
+                 profile=False, debug_flags=0, graph=True, max_wg_per_subset=0, est_error=False):
         """Arrays are numpy-like (host) or, when locs is a torch tensor on the
         GPU, torch tensors on that device (the library's inputs_on_device
         option); predict then takes and returns device tensors too."""
@@ -291,6 +292,7 @@ class Problem:
         opt.mem_cap_bytes = int(mem_cap)
         opt.profile = 1 if profile else 0
         opt.debug_flags = int(debug_flags)
+        opt.est_error = 1 if est_error else 0
         opt.graph = 1 if graph else 0
         opt.inputs_on_device = 1 if self.on_device else 0
         opt.max_wg_per_subset = int(max_wg_per_subset)

@@ -116,6 +116,7 @@ void sequence(const Data& d, int rep) {
   const Live base = Live::now();
   pcv_options o;
   pcv_default_options(&o);
+  o.est_error = rep % 2;  // every other cycle with the error estimate's extra pass
   pcv_problem* p = create(d, o);
   evals(p, 3);
   std::vector<pcv_theta> ths;

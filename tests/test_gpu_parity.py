@@ -295,6 +295,39 @@ def test_second_sweep_only_where_residual_above_tol(w_batched_small, graph):
     np.testing.assert_array_equal(batch, single)
 
 
+@pytest.mark.parametrize("max_refine", [0, 1, 2])
+def test_error_estimate_tracks_fp64(w_batched_small, max_refine):
+    """est_rel_err, the loss change one more refinement sweep makes, against
+    the measured relative difference from the FP64 path.  With no sweep the
+    FP32 solve's error dominates and the two agree within 25% (the
+    refinement contracts the error by far more); with sweeps both are tiny
+    and the estimate stays within a factor 3 of the measured difference or
+    below 1e-13 (the FP64 path's own rounding).  The estimate leaves the
+    result bit for bit as it is, reads -1 when not asked for and 0 for an
+    FP64 problem."""
+    w = w_batched_small
+    th = pcv.theta(w.theta_true[0], w.theta_true[1] / 2)
+    say(f"[case] error estimate max_refine={max_refine}")
+    with pcv.Problem.from_workload(w, prec="fp64", est_error=True) as P:
+        l64, r64 = P.eval(th, report=True)
+    assert r64["est_rel_err"] == 0.0
+    with pcv.Problem.from_workload(w, prec="mixed", max_refine=max_refine) as P:
+        l0, r0 = P.eval(th, report=True)
+    assert r0["est_rel_err"] == -1.0
+    with pcv.Problem.from_workload(w, prec="mixed", max_refine=max_refine, est_error=True) as P:
+        l1, r1 = P.eval(th, report=True)
+        l2 = P.eval(th, report=True)[0]
+    assert l1 == l0 == l2
+    np.testing.assert_array_equal(r1["per_subset_sspe"], r0["per_subset_sspe"])
+    est, act = r1["est_rel_err"], _rel(l1, l64)
+    say(f"   estimated {est:.3e}  measured against the FP64 path {act:.3e}")
+    assert est >= 0.0
+    if max_refine == 0:
+        assert act > 1e-9 and 0.8 * act <= est <= 1.25 * act
+    else:
+        assert est <= max(3 * act, 1e-13) and act <= max(3 * est, 1e-13)
+
+
 @pytest.mark.parametrize("lam", [1e-3, 3e-4])
 def test_small_nugget_second_sweep_avoids_fallback(w_plain, lam):
     """Small nugget: the FP32 factor is poorly conditioned, so a subset's
