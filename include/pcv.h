@@ -212,7 +212,7 @@ void pcv_default_options(pcv_options* opt);
  * maximum (PCV_MAX_SUBSET training points) is rejected with PCV_ERR_INVALID.
  * Errors: PCV_ERR_INVALID (sizes, NaN/Inf, index range, ptr order),
  * PCV_ERR_OOM, PCV_ERR_DEVICE. */
-#define PCV_MAX_SUBSET 16384
+#define PCV_MAX_SUBSET 16320
 pcv_status pcv_problem_create(pcv_problem** out, int64_t n, const double* locs,
                               const double* y, int32_t S, const int64_t* train_ptr,
                               const int32_t* train_idx, const int64_t* val_ptr,

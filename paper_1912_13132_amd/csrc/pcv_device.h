@@ -87,6 +87,8 @@ struct CoopPlan {
   int n_blocks;
   int32_t* sync;
   int n_slots;
+  const int32_t* subsets;  // the launch's subsets, each once (the order list
+  int n_subsets;           // repeats shared ones), for the y_T row's move-out
 };
 // max_npad: the largest padded size among the listed subsets.  FP32 launches
 // with max_npad <= small_npad use workgroups of 4 waves (64-column panels,
@@ -100,13 +102,18 @@ constexpr int FACTOR_SMALL_NPAD = 1536;
 // measured on uniform sizes: faster up to n = 600, equal at 700, slower
 // from 800.
 constexpr int FACTOR_TINY_NPAD = 704;
+// cv (may be null): the subsets' y_T values in the coordinates' padded
+// layout; then each subset's first padding row (row n) carries them through
+// the factorisation and zout receives z = L^{-1} y_T (FP64, at offP, zeros
+// from n to npad), the forward substitution of the solve, while the factor
+// comes out as without them.  Needs npad > n for every subset with n > 0.
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
-                            const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp = nullptr,
+                            const float* cy, const float* cv, double* zout, float* Lbuf, double* Inv,
+                            double* logdet, int32_t* status, const CoopPlan* cp = nullptr,
                             int small_npad = FACTOR_SMALL_NPAD, int tiny_npad = FACTOR_TINY_NPAD);
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
-                            const double* cy, double* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp = nullptr);
+                            const double* cy, const double* cv, double* zout, double* Lbuf, double* Inv,
+                            double* logdet, int32_t* status, const CoopPlan* cp = nullptr);
 // max_npad: the largest padded size among the launched subsets (selects the
 // per-thread register budget of the solve kernels).
 // gate (may be null): per descriptor, 0 = skip this subset (a refinement

@@ -142,6 +142,10 @@ struct pcv_problem {
   // factorisation coordinates, padded to npad per subset with +inf (offP)
   double *d_px64 = nullptr, *d_py64 = nullptr;
   float *d_px32 = nullptr, *d_py32 = nullptr;
+  // y_T in the same padded layout (zeros in padding): the factorisation's
+  // y_T row (forward substitution)
+  double* d_pv64 = nullptr;
+  float* d_pv32 = nullptr;
   double *d_vx = nullptr, *d_vy = nullptr, *d_yV = nullptr;
   double *d_z = nullptr, *d_x = nullptr, *d_alpha = nullptr, *d_r = nullptr, *d_rhs2 = nullptr;
   double *d_yhat = nullptr, *d_err = nullptr;

@@ -112,6 +112,11 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 constexpr int WR = 32;    // chunk rows per wave
+// Diagonal of the y_T row: far above any |L^{-1} y_T|^2 part its block
+// subtracts, so that its pivot stays positive and the padding rows below it
+// keep zero entries in its column (a pivot there that fails anyway is set to
+// 1 and not reported: the row is not part of the subset matrix).
+constexpr double VDIAG = 1e200;
 constexpr int NBJ = WR / 16;
 constexpr int LDD = 65;   // FP64 diagonal array row stride (doubles)
 
@@ -279,7 +284,7 @@ __device__ void diag_factor_invert(double (*Dg)[LDD], double (*Tb)[16][17], int 
         double p = rlane(a[uj], 4 * j + qj);
         const bool ok = p > 0.0 && p < 1e300;
         if (!ok) p = 1.0;
-        if (l == 0 && !ok && !bad) bad = grow0 + k0 + j + 1;
+        if (l == 0 && !ok && !bad && k0 + j < nreal) bad = grow0 + k0 + j + 1;
         double isp = __builtin_amdgcn_rsq(p);
         isp = isp * (1.5 - 0.5 * p * isp * isp);
         isp = isp * (1.5 - 0.5 * p * isp * isp);
@@ -436,11 +441,37 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// After a factorisation with the y_T row: z = L^{-1} y_T (FP64, padded with
+// zeros to npad) from row n, then row n and its row of the diagonal-block
+// inverse are reset to those of a padding row (unit diagonal, zeros).
+template <typename T>
+__global__ __launch_bounds__(256) void k_take_z(const SubsetDesc* __restrict__ desc,
+                                                const int32_t* __restrict__ order, T* __restrict__ Lbuf,
+                                                double* __restrict__ Invbuf, double* __restrict__ zbuf) {
+  const SubsetDesc D = desc[order[blockIdx.x]];
+  const int n = D.n, npad = D.npad;
+  if (n <= 0 || n >= npad) return;
+  T* __restrict__ row = Lbuf + D.offL + packed_rowoff32(n);
+  double* __restrict__ z = zbuf + D.offP;
+  for (int i = threadIdx.x; i < npad; i += 256) {
+    if (i < n) {
+      z[i] = (double)row[i];
+      row[i] = (T)0;
+    } else {
+      z[i] = 0.0;
+      if (i == n) row[i] = (T)1;
+    }
+  }
+  double* __restrict__ inv = Invbuf + D.offInv + (int64_t)(n / 64) * 4096 + (n % 64) * 64;
+  for (int j = threadIdx.x; j < 64; j += 256) inv[j] = j == n % 64 ? 1.0 : 0.0;
+}
+
 template <typename T, int NTH, bool COOP>
 __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order,
                                                  const ThetaDev* __restrict__ theta,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
+                                                 const T* __restrict__ cyv,
                                                  T* __restrict__ Lbuf, double* __restrict__ Invbuf,
                                                  double* __restrict__ logdet,
                                                  int32_t* __restrict__ status,
@@ -460,6 +491,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   __shared__ __attribute__((aligned(16))) T InvS[SM::NINV > 0 ? SM::NINV : 1][SM::NINV > 0 ? 64 * LDI : 1];
   __shared__ double TbS[SM::TINY ? 1 : 3][16][17];
   __shared__ T colx[PB], coly[PB];  // the current panel's column coordinates
+  __shared__ T colv[PB];            // ... and their y_T values (row n, when cyv is given)
 
   T* Ps = reinterpret_cast<T*>(smem_u);    // [PB][LDK]  panel rows (negated)
   T* L21s = reinterpret_cast<T*>(smem_u);  // [64][LDI]  -L21 (second half update)
@@ -491,6 +523,11 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   double* __restrict__ Inv = Invbuf + D.offInv;
   const T* __restrict__ X = cx + D.offX;  // padded coordinates (npad entries)
   const T* __restrict__ Y = cy + D.offX;
+  // With cyv, the training values y_T ride along as row n (the first padding
+  // row): entries y_j in columns j < n, a large diagonal.  The left-looking
+  // updates and panel solves then leave (L^{-1} y_T)_j in that row, the
+  // forward substitution of the solve of eq. (3); rows < n never read it,
+  // so their factor is unchanged.  The row is moved out afterwards.
   const int cov = theta[D.th].cov;
   const T ir = (T)theta[D.th].inv_range;
   const double lam64 = theta[D.th].lambda;
@@ -513,6 +550,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
       const int col = min(c0 + tid, npad - 1);
       colx[tid] = X[col];
       coly[tid] = Y[col];
+      colv[tid] = cyv ? cyv[(X - cx) + col] : (T)0;
     }
     for (int r0 = c0 + RCH * rank; r0 < npad; r0 += RCH * nwg) {
       const bool first = (r0 == c0);
@@ -643,6 +681,20 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
         }
       }
 
+      // the y_T row (a padding row, so its covariance entries are 0): add
+      // y_j after the update, in the one lane row of the one wave that holds it
+      if (cyv && wact && n >= wr0 && n < wr0 + WR) {
+        const int rn = n - wr0;
+#pragma unroll
+        for (int bj = 0; bj < NBJ; ++bj)
+          if ((rn >> 4) == bj && lr == (rn & 15)) {
+#pragma unroll
+            for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[bi][bj][v] += colv[16 * bi + Cfg<T>::crow(g, v)];
+          }
+      }
+
       if constexpr (COOP) {
         if (!inv_ready) {
           // rank 0 has stored this panel's diagonal chunk (factor rows and
@@ -673,7 +725,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
                 Dg[WR * wpos + 16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[bi][bj][v];
         }
         __syncthreads();
-        if (tid < 64) Dg[tid][tid] = c0 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
+        if (tid < 64) Dg[tid][tid] = c0 + tid < n ? Dg[tid][tid] + lam64 : (cyv && c0 + tid == n ? VDIAG : 1.0);
         __syncthreads();
         diag_factor_invert<SM::NW>(Dg, Tb, n - c0, c0, ld, bad);
         for (int e = tid; e < 64 * 64; e += NT) {
@@ -758,7 +810,8 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
                     Dg[WR * (wpos - 2) + 16 * bj + lr][16 * bi + Cfg<T>::crow(g, v)] = (double)acc[4 + bi][bj][v];
             }
             __syncthreads();
-            if (tid < 64) Dg[tid][tid] = c0 + 64 + tid < n ? Dg[tid][tid] + lam64 : 1.0;
+            if (tid < 64)
+              Dg[tid][tid] = c0 + 64 + tid < n ? Dg[tid][tid] + lam64 : (cyv && c0 + 64 + tid == n ? VDIAG : 1.0);
             __syncthreads();
             diag_factor_invert<SM::NW>(Dg, Tb, n - c0 - 64, c0 + 64, ld, bad);
             for (int e = tid; e < 64 * 64; e += NT) {
@@ -825,43 +878,55 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
 }  // namespace potrf
 
 template <typename T>
+static hipError_t take_z(const Launch& Lc, const int32_t* order, int n_items, const T* cv, T* Lbuf, double* Inv,
+                         double* zout) {
+  if (!cv || n_items <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(potrf::k_take_z<T>, dim3(n_items), dim3(256), 0, Lc.stream, Lc.desc, order, Lbuf, Inv, zout);
+  return hipGetLastError();
+}
+
+template <typename T>
 static hipError_t potrf2_launch(const Launch& Lc, const int32_t* order, int n_items, const T* cx,
-                                const T* cy, T* Lbuf, double* Inv, double* logdet, int32_t* status,
-                                const CoopPlan* cp) {
+                                const T* cy, const T* cv, double* zout, T* Lbuf, double* Inv, double* logdet,
+                                int32_t* status, const CoopPlan* cp) {
   if (n_items <= 0) return hipSuccess;
   if (cp && cp->n_blocks > 0) {
     if (cp->n_blocks > n_items || cp->n_slots <= 0 || !cp->info || !cp->sync) return hipErrorInvalidValue;
     const int nz = 4 * cp->n_slots;
     hipLaunchKernelGGL(potrf::k_fill_i32, dim3((nz + 255) / 256), dim3(256), 0, Lc.stream, cp->sync, nz, 0);
+    if (cv && (!cp->subsets || cp->n_subsets <= 0)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((potrf::k_potrf<T, 512, true>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order,
-                       Lc.theta, cx, cy, Lbuf, Inv, logdet, status, cp->info, cp->n_blocks, cp->sync);
-    return hipGetLastError();
+                       Lc.theta, cx, cy, cv, Lbuf, Inv, logdet, status, cp->info, cp->n_blocks, cp->sync);
+    return take_z<T>(Lc, cp->subsets, cp->n_subsets, cv, Lbuf, Inv, zout);
+  } else {
+    hipLaunchKernelGGL((potrf::k_potrf<T, 512, false>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order,
+                       Lc.theta, cx, cy, cv, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
   }
-  hipLaunchKernelGGL((potrf::k_potrf<T, 512, false>), dim3(n_items), dim3(512), 0, Lc.stream, Lc.desc, order,
-                     Lc.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
-  return hipGetLastError();
+  return take_z<T>(Lc, order, n_items, cv, Lbuf, Inv, zout);
 }
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n_items, int max_npad, const float* cx,
-                            const float* cy, float* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp, int small_npad, int tiny_npad) {
+                            const float* cy, const float* cv, double* zout, float* Lbuf, double* Inv,
+                            double* logdet, int32_t* status, const CoopPlan* cp, int small_npad, int tiny_npad) {
+  if (cv && !zout) return hipErrorInvalidValue;
   if (n_items > 0 && max_npad <= tiny_npad) {
     if (cp && cp->n_blocks > 0) return hipErrorInvalidValue;  // cooperative ranks use 8-wave workgroups
     hipLaunchKernelGGL((potrf::k_potrf<float, 128, false>), dim3(n_items), dim3(128), 0, L.stream, L.desc, order,
-                       L.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
-    return hipGetLastError();
+                       L.theta, cx, cy, cv, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
+    return take_z<float>(L, order, n_items, cv, Lbuf, Inv, zout);
   }
   if (n_items > 0 && max_npad <= small_npad) {
     if (cp && cp->n_blocks > 0) return hipErrorInvalidValue;  // cooperative ranks use 8-wave workgroups
     hipLaunchKernelGGL((potrf::k_potrf<float, 256, false>), dim3(n_items), dim3(256), 0, L.stream, L.desc, order,
-                       L.theta, cx, cy, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
-    return hipGetLastError();
+                       L.theta, cx, cy, cv, Lbuf, Inv, logdet, status, nullptr, 0, nullptr);
+    return take_z<float>(L, order, n_items, cv, Lbuf, Inv, zout);
   }
-  return potrf2_launch<float>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status, cp);
+  return potrf2_launch<float>(L, order, n_items, cx, cy, cv, zout, Lbuf, Inv, logdet, status, cp);
 }
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n_items, const double* cx,
-                            const double* cy, double* Lbuf, double* Inv, double* logdet,
-                            int32_t* status, const CoopPlan* cp) {
-  return potrf2_launch<double>(L, order, n_items, cx, cy, Lbuf, Inv, logdet, status, cp);
+                            const double* cy, const double* cv, double* zout, double* Lbuf, double* Inv,
+                            double* logdet, int32_t* status, const CoopPlan* cp) {
+  if (cv && !zout) return hipErrorInvalidValue;
+  return potrf2_launch<double>(L, order, n_items, cx, cy, cv, zout, Lbuf, Inv, logdet, status, cp);
 }
 
 }  // namespace pcv

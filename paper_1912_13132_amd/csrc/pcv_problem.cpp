@@ -332,7 +332,9 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
     SubsetDesc& d = p->desc[i];
     d.n = (int32_t)(tptr[i + 1] - tptr[i]);
     d.m = (int32_t)(vptr[i + 1] - vptr[i]);
-    d.npad = (d.n + TB - 1) / TB * TB;
+    // at least one padding row: the first one carries y_T through the
+    // factorisation (the forward substitution, see launch_potrf_*)
+    d.npad = d.n > 0 ? (d.n / TB + 1) * TB : 0;
     d.th = 0;
     d.offT = offT;
     d.offV = offV;
@@ -407,6 +409,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   std::vector<double> tx(offT), ty(offT), yT(offT), vx(offV), vy(offV), yV(offV);
   std::vector<double> px64(offP, INFINITY), py64(offP, INFINITY);
   std::vector<float> px32(offP, INFINITY), py32(offP, INFINITY);
+  std::vector<double> pv64(offP, 0.0);  // y_T in the padded layout
+  std::vector<float> pv32(offP, 0.0f);
   for (int32_t i = 0; i < S; ++i) {
     const SubsetDesc& d = p->desc[i];
     double cx = 0.0, cy = 0.0;
@@ -437,6 +441,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
       px32[d.offP + a] = (float)tx[d.offT + a];
       py32[d.offP + a] = (float)ty[d.offT + a];
       yT[d.offT + a] = y[g];
+      pv64[d.offP + a] = y[g];
+      pv32[d.offP + a] = (float)y[g];
       y2 += y[g] * y[g];
     }
     p->ynorm2[i] = y2;
@@ -467,6 +473,8 @@ pcv_status problem_build(pcv_problem* p, int64_t n, const double* locs, const do
   TRY(upload(p, &p->d_yT, yT));
   TRY(upload(p, &p->d_px32, px32));
   TRY(upload(p, &p->d_py32, py32));
+  TRY(upload(p, &p->d_pv64, pv64));
+  TRY(upload(p, &p->d_pv32, pv32));
   TRY(upload(p, &p->d_px64, px64));
   TRY(upload(p, &p->d_py64, py64));
   TRY(upload(p, &p->d_vx, vx));
@@ -632,8 +640,8 @@ pcv_status factor_solve64(pcv_problem* p, const SubsetDesc* d_desc, const ThetaD
                           const int32_t* d_order, int count, double* Lb, double* Invb, double* zb,
                           double* alphab, double* logdetb, int32_t* statusb) {
   Launch Lc{p->stream, d_desc, d_theta};
-  HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_px64, p->d_py64, Lb, Invb, logdetb, statusb));
-  HIPCHK(launch_trsv_fwd_f64(Lc, d_order, count, p->max_npad, Lb, Invb, p->d_yT, nullptr, zb, nullptr));
+  // z = L^{-1} y_T from the factorisation's y_T row
+  HIPCHK(launch_potrf_f64(Lc, d_order, count, p->d_px64, p->d_py64, p->d_pv64, zb, Lb, Invb, logdetb, statusb));
   HIPCHK(launch_trsv_bwd_f64(Lc, d_order, count, p->max_npad, Lb, Invb, zb, alphab, nullptr));
   return PCV_OK;
 }
@@ -715,14 +723,15 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
     case 1:
       if (p->coop_now && G.o0 == 0 && cnt == p->coop_group_cnt) {
         // the first launch with its largest subsets shared by several work-groups
-        const CoopPlan cp{p->d_coop_info, p->coop_blocks, p->d_coop_sync, p->coop_slots};
+        const CoopPlan cp{p->d_coop_info, p->coop_blocks, p->d_coop_sync, p->coop_slots, p->d_order_eval, cnt};
         const int nb = (int)p->coop_order.size();
         if (mixed)
           HIPCHK(launch_potrf_f32(Lc, p->d_coop_order, nb, p->desc[p->order_eval[0]].npad, p->d_px32,
-                                  p->d_py32, p->d_L32, p->d_Inv, p->d_logdet, p->d_status, &cp));
+                                  p->d_py32, p->d_pv32, p->d_z, p->d_L32, p->d_Inv, p->d_logdet, p->d_status,
+                                  &cp));
         else
-          HIPCHK(launch_potrf_f64(Lc, p->d_coop_order, nb, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
-                                  p->d_logdet, p->d_status, &cp));
+          HIPCHK(launch_potrf_f64(Lc, p->d_coop_order, nb, p->d_px64, p->d_py64, p->d_pv64, p->d_z, p->d_L64,
+                                  p->d_Inv, p->d_logdet, p->d_status, &cp));
         break;
       }
       // the part of each schedule group inside G, in launches of
@@ -733,27 +742,23 @@ pcv_status enqueue_phase(pcv_problem* p, hipStream_t st, int phase, bool mixed, 
         for (int32_t c0 = a; c0 < e; c0 += factor_chunk(p, e - a)) {
           const int32_t c = std::min(factor_chunk(p, e - a), e - c0);
           if (mixed)
-            HIPCHK(launch_potrf_f32(Lc, p->d_order_eval + c0, c, sched_npad(p, k), p->d_px32, p->d_py32, p->d_L32,
-                                    p->d_Inv, p->d_logdet, p->d_status, nullptr, p->tune_small_npad));
+            HIPCHK(launch_potrf_f32(Lc, p->d_order_eval + c0, c, sched_npad(p, k), p->d_px32, p->d_py32, p->d_pv32,
+                                    p->d_z, p->d_L32, p->d_Inv, p->d_logdet, p->d_status, nullptr,
+                                    p->tune_small_npad));
           else
-            HIPCHK(launch_potrf_f64(Lc, p->d_order_eval + c0, c, p->d_px64, p->d_py64, p->d_L64, p->d_Inv,
-                                    p->d_logdet, p->d_status));
+            HIPCHK(launch_potrf_f64(Lc, p->d_order_eval + c0, c, p->d_px64, p->d_py64, p->d_pv64, p->d_z, p->d_L64,
+                                    p->d_Inv, p->d_logdet, p->d_status));
           PACE();
         }
       }
       break;
     case 2:
+      // z = L^{-1} y_T came out of the factorisation (the y_T row)
       if (mixed) {
-        HIPCHK(launch_trsv_fwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_yT,
-                                   nullptr, p->d_z, nullptr));
-        PACE();
         HIPCHK(launch_trsv_bwd_f32(Lc, order, cnt, p->max_npad, p->d_L32, p->d_Inv, p->d_z,
                                    p->d_alpha, nullptr));
         PACE();
       } else {
-        HIPCHK(launch_trsv_fwd_f64(Lc, order, cnt, p->max_npad, p->d_L64, p->d_Inv, p->d_yT,
-                                   nullptr, p->d_z, nullptr));
-        PACE();
         HIPCHK(launch_trsv_bwd_f64(Lc, order, cnt, p->max_npad, p->d_L64, p->d_Inv, p->d_z,
                                    p->d_alpha, nullptr));
         PACE();
@@ -1265,13 +1270,12 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
       const int32_t ck = factor_chunk(p, e - a);
       for (int32_t c0 = a; c0 < e; c0 += ck) {
         HIPCHK(launch_potrf_f32(Lc, pl.d_order + c0, std::min(ck, e - c0), sched_npad(p, k), p->d_px32, p->d_py32,
-                                L, b.d_Inv, b.d_logdet, b.d_status, nullptr, p->tune_small_npad));
+                                p->d_pv32, b.d_z, L, b.d_Inv, b.d_logdet, b.d_status, nullptr,
+                                p->tune_small_npad));
         HIPCHK(pace());
       }
     }
     if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
-    HIPCHK(launch_trsv_fwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));
-    HIPCHK(pace());
     HIPCHK(launch_trsv_bwd_f32(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_alpha, nullptr));
     HIPCHK(pace());
     if (ev) HIPCHK(hipEventRecord(p->ev[2], st));
@@ -1295,13 +1299,11 @@ pcv_status enqueue_batch(pcv_problem* p, const pcv_batch_plan& pl, hipStream_t s
   } else {
     double* L = (double*)b.d_L;
     for (int32_t c0 = 0; c0 < pl.n_order; c0 += chunk) {
-      HIPCHK(launch_potrf_f64(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0), p->d_px64, p->d_py64, L,
-                              b.d_Inv, b.d_logdet, b.d_status));
+      HIPCHK(launch_potrf_f64(Lc, pl.d_order + c0, std::min(chunk, pl.n_order - c0), p->d_px64, p->d_py64,
+                              p->d_pv64, b.d_z, L, b.d_Inv, b.d_logdet, b.d_status));
       HIPCHK(pace());
     }
     if (ev) HIPCHK(hipEventRecord(p->ev[1], st));
-    HIPCHK(launch_trsv_fwd_f64(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, p->d_yT, nullptr, b.d_z, nullptr));
-    HIPCHK(pace());
     HIPCHK(launch_trsv_bwd_f64(Lc, pl.d_order, pl.n_order, p->max_npad, L, b.d_Inv, b.d_z, b.d_alpha, nullptr));
     HIPCHK(pace());
     if (ev) HIPCHK(hipEventRecord(p->ev[2], st));

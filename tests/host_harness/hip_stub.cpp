@@ -468,35 +468,39 @@ static void launched(const char* what, std::function<void()> chk, hipStream_t s)
   enqueue(s, what, chk);  // and when it runs (graph replays)
 }
 
+static void potrf_checks(const Launch& L, const int32_t* order, int n, const void* cx, const void* cy,
+                         const void* cv, double* zout, const void* Lb, double* Inv, double* logdet,
+                         int32_t* status, const CoopPlan& c) {
+  dev_ptr(L.desc, "potrf desc"); dev_ptr(L.theta, "potrf theta"); dev_range(order, 4 * (size_t)n, "potrf order");
+  dev_ptr(cx, "potrf cx"); dev_ptr(cy, "potrf cy"); dev_ptr(cv, "potrf cv"); dev_ptr(zout, "potrf z");
+  dev_ptr(Lb, "potrf L"); dev_ptr(Inv, "potrf Inv");
+  dev_ptr(logdet, "potrf logdet"); dev_ptr(status, "potrf status");
+  if (c.n_blocks > 0) {
+    dev_range(c.info, 4 * (size_t)c.n_blocks, "potrf coop info");
+    dev_range(c.sync, 16 * (size_t)c.n_slots, "potrf coop sync");
+    if (cv) dev_range(c.subsets, 4 * (size_t)c.n_subsets, "potrf coop subsets");
+  }
+}
 hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n, int, const float* cx, const float* cy,
-                            float* Lb, double* Inv, double* logdet, int32_t* status, const CoopPlan* cp, int,
-                            int) {
+                            const float* cv, double* zout, float* Lb, double* Inv, double* logdet, int32_t* status,
+                            const CoopPlan* cp, int, int) {
+  if (cv && !zout) return hipErrorInvalidValue;
   if (n <= 0) return hipSuccess;
   const CoopPlan c = cp ? *cp : CoopPlan{};
-  launched("potrf_f32", [=] {
-    dev_ptr(L.desc, "potrf desc"); dev_ptr(L.theta, "potrf theta"); dev_range(order, 4 * (size_t)n, "potrf order");
-    dev_ptr(cx, "potrf cx"); dev_ptr(cy, "potrf cy"); dev_ptr(Lb, "potrf L"); dev_ptr(Inv, "potrf Inv");
-    dev_ptr(logdet, "potrf logdet"); dev_ptr(status, "potrf status");
-    if (c.n_blocks > 0) {
-      dev_range(c.info, 4 * (size_t)c.n_blocks, "potrf coop info");
-      dev_range(c.sync, 16 * (size_t)c.n_slots, "potrf coop sync");
-    }
-  }, L.stream);
+  if (cv && c.n_blocks > 0 && (!c.subsets || c.n_subsets <= 0)) return hipErrorInvalidValue;
+  launched("potrf_f32", [=] { potrf_checks(L, order, n, cx, cy, cv, zout, Lb, Inv, logdet, status, c); },
+           L.stream);
   return hipSuccess;
 }
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n, const double* cx, const double* cy,
-                            double* Lb, double* Inv, double* logdet, int32_t* status, const CoopPlan* cp) {
+                            const double* cv, double* zout, double* Lb, double* Inv, double* logdet,
+                            int32_t* status, const CoopPlan* cp) {
+  if (cv && !zout) return hipErrorInvalidValue;
   if (n <= 0) return hipSuccess;
   const CoopPlan c = cp ? *cp : CoopPlan{};
-  launched("potrf_f64", [=] {
-    dev_ptr(L.desc, "potrf desc"); dev_ptr(L.theta, "potrf theta"); dev_range(order, 4 * (size_t)n, "potrf order");
-    dev_ptr(cx, "potrf cx"); dev_ptr(cy, "potrf cy"); dev_ptr(Lb, "potrf L"); dev_ptr(Inv, "potrf Inv");
-    dev_ptr(logdet, "potrf logdet"); dev_ptr(status, "potrf status");
-    if (c.n_blocks > 0) {
-      dev_range(c.info, 4 * (size_t)c.n_blocks, "potrf coop info");
-      dev_range(c.sync, 16 * (size_t)c.n_slots, "potrf coop sync");
-    }
-  }, L.stream);
+  if (cv && c.n_blocks > 0 && (!c.subsets || c.n_subsets <= 0)) return hipErrorInvalidValue;
+  launched("potrf_f64", [=] { potrf_checks(L, order, n, cx, cy, cv, zout, Lb, Inv, logdet, status, c); },
+           L.stream);
   return hipSuccess;
 }
 template <typename T>
