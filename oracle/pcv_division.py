@@ -202,3 +202,23 @@ def subsets(locs, core_rect, delta, is_val=None):
     tidx = np.concatenate(train).astype(np.int32) if S else np.zeros(0, np.int32)
     vidx = np.concatenate(val).astype(np.int32) if S else np.zeros(0, np.int32)
     return owner.astype(np.int32), tptr, tidx, vptr, vidx
+
+
+def kfold_subsets(locs, core_rect, delta, labels, k):
+    """Parallel k-fold CV (the remark closing Sec. 2.2), read as k rounds of
+    the hold-out CV of Sec. 2.3: round j holds out every point whose fold
+    label is j.  Returns the subsets of all rounds concatenated round-major
+    (subset j * S + i = core i in round j), as (train_ptr, train_idx,
+    val_ptr, val_idx); the summed SSPE over them is the k-fold loss.
+    labels: int (N,) fold of every point, an input (the draw is not part of
+    the method)."""
+    labels = np.asarray(labels)
+    tp_all, ti_all, vp_all, vi_all = [np.zeros(1, np.int64)], [], [np.zeros(1, np.int64)], []
+    for j in range(k):
+        _, tp, ti, vp, vi = subsets(locs, core_rect, delta, is_val=labels == j)
+        tp_all.append(tp[1:] + tp_all[-1][-1])
+        vp_all.append(vp[1:] + vp_all[-1][-1])
+        ti_all.append(ti)
+        vi_all.append(vi)
+    return (np.concatenate(tp_all), np.concatenate(ti_all).astype(np.int32),
+            np.concatenate(vp_all), np.concatenate(vi_all).astype(np.int32))

@@ -25,6 +25,14 @@ recursive_cores, count_memberships and build_partition take device=True to
 run the geometry on the GPU (the library's pcv_part_* calls), with results
 identical to the host code; the random hold-out split and the cap are drawn
 on the host in both cases.
+
+Parallel k-fold CV (the remark closing Sec. 2.2): every point gets a fold
+label, drawn per core (a random permutation of the core's points cut into k
+folds whose sizes differ by at most one); round j holds out the points
+labelled j everywhere, so that its subsets are the hold-out subsets of
+Sec. 2.3 for that split (shells drop held-out points too).  The k rounds
+become one problem of k * S subsets, round-major, whose summed loss is the
+k-fold loss: every point is predicted once, in the round that holds it out.
 """
 from dataclasses import dataclass, field
 
@@ -324,6 +332,80 @@ def build_partition(P, core_rect, delta, val_frac, rng, cap=None, device=False):
                 val_total=int(vptr[-1]))
     return Partition(core_rect=R, delta=float(delta), train_ptr=tptr, train_idx=tidx,
                      val_ptr=vptr, val_idx=vidx, owner=owner, is_val=is_val, info=info)
+
+
+def kfold_labels(owner, S, k, rng):
+    """Fold label (0..k-1) of every point: per core, in core order, a random
+    permutation of its points (increasing index) cut into k consecutive
+    folds of sizes differing by at most one."""
+    owner = np.asarray(owner)
+    if k < 2:
+        raise ValueError("k-fold CV needs k >= 2")
+    order = np.argsort(owner, kind="stable")
+    starts = np.searchsorted(owner[order], np.arange(S + 1))
+    labels = np.zeros(owner.shape[0], dtype=np.int32)
+    for i in range(S):
+        members = order[starts[i]:starts[i + 1]]
+        perm = members[rng.permutation(members.shape[0])]
+        labels[perm] = (np.arange(members.shape[0]) * k) // max(members.shape[0], 1)
+    return labels
+
+
+def build_partition_kfold(P, core_rect, delta, k, rng, device=False):
+    """Parallel k-fold CV: the hold-out subsets of every round j (points
+    labelled j held out, kfold_labels), concatenated round-major into one
+    Partition of k * S subsets (subset j * S + i: core i in round j; core
+    rectangles repeated).  is_val marks nothing; info["labels"] holds the
+    fold of every point."""
+    P = np.asarray(P, dtype=np.float64)
+    R = np.asarray(core_rect, dtype=np.float64)
+    S = R.shape[0]
+    if device:
+        from . import pcv
+        owner = pcv.part_subsets(P, R, delta, lists=False)
+    else:
+        owner = assign_cores(P, R)
+    labels = kfold_labels(owner, S, k, rng)
+    rounds = []
+    for j in range(k):
+        held = labels == j
+        if device:
+            _, tp, ti, vp, vi = pcv.part_subsets(P, R, delta, is_val=held)
+        else:
+            tp, ti, vp, vi = _subsets_for_split(P, R, delta, owner, held)
+        rounds.append((tp, ti, vp, vi))
+    tptr = np.zeros(k * S + 1, dtype=np.int64)
+    vptr = np.zeros(k * S + 1, dtype=np.int64)
+    for j, (tp, _, vp, _) in enumerate(rounds):
+        tptr[j * S + 1:(j + 1) * S + 1] = tp[1:] + tptr[j * S]
+        vptr[j * S + 1:(j + 1) * S + 1] = vp[1:] + vptr[j * S]
+    tidx = np.concatenate([r[1] for r in rounds]).astype(np.int32)
+    vidx = np.concatenate([r[3] for r in rounds]).astype(np.int32)
+    info = dict(k=int(k), labels=labels, memberships=int(tptr[-1] + vptr[-1]),
+                train_min=int(np.diff(tptr).min()), train_max=int(np.diff(tptr).max()),
+                val_total=int(vptr[-1]))
+    return Partition(core_rect=np.tile(R, (k, 1)), delta=float(delta), train_ptr=tptr, train_idx=tidx,
+                     val_ptr=vptr, val_idx=vidx, owner=owner, is_val=np.zeros(P.shape[0], dtype=bool),
+                     info=info)
+
+
+def _subsets_for_split(P, R, delta, owner, is_val):
+    """Host CSR of the subsets for a given hold-out mask (no cap)."""
+    S = R.shape[0]
+    order = np.argsort(owner, kind="stable")
+    starts = np.searchsorted(owner[order], np.arange(S + 1))
+    domain = (R[:, 0].min(), R[:, 1].min(), R[:, 2].max(), R[:, 3].max())
+    shells = _shell_members(P, R, delta, ~is_val, _Buckets(P, domain))
+    train, val = [], []
+    for i in range(S):
+        members = order[starts[i]:starts[i + 1]]
+        train.append(np.sort(np.concatenate([members[~is_val[members]], shells[i]])))
+        val.append(members[is_val[members]])
+    tptr = np.r_[0, np.cumsum([t.shape[0] for t in train])].astype(np.int64)
+    vptr = np.r_[0, np.cumsum([v.shape[0] for v in val])].astype(np.int64)
+    tidx = np.concatenate(train).astype(np.int32) if S else np.zeros(0, np.int32)
+    vidx = np.concatenate(val).astype(np.int32) if S else np.zeros(0, np.int32)
+    return tptr, tidx, vptr, vidx
 
 
 def _split(owner, S, val_frac, rng):
