@@ -152,6 +152,11 @@ struct pcv_problem {
   double *d_logdet = nullptr, *d_sspe = nullptr, *d_quad = nullptr;
   int32_t* d_status = nullptr;
   int32_t* d_bad = nullptr;         // subsets re-run in FP64
+  // mixed path: FP64 factors of the re-run subsets only, packed one after
+  // the other (grow-only), and descriptors pointing into it
+  double* d_L64fb = nullptr;
+  int64_t L64fb_cap = 0;
+  pcv::SubsetDesc* d_desc_fb = nullptr;
   int32_t *d_gate = nullptr, *d_nsweep = nullptr;  // refinement sweeps taken, per subset
   // error estimate (opt.est_error): predictions, squared errors, per-subset
   // SSPE and total from alpha after one more sweep; allocated on first use

@@ -1018,14 +1018,28 @@ pcv_status eval_impl(pcv_problem* p, const pcv_theta& th, double* loss, pcv_eval
       return fail(PCV_ERR_NOT_PD, "subset " + std::to_string(bad[0]) + " is not positive definite (pivot " +
                                       std::to_string(status[bad[0]] - 1) + ")");
     }
-    // FP64 re-run of the subsets whose FP32 factorisation broke down
+    // FP64 re-run of the subsets whose FP32 factorisation broke down, their
+    // FP64 factors packed into a buffer sized for them alone
     n_fallback = (int32_t)bad.size();
     fb_list = bad;
-    s = ensure_L(p, true);
-    if (s != PCV_OK) return s;
+    std::vector<SubsetDesc> dfb = p->desc;
+    int64_t need = 0;
+    for (int32_t i : bad) {
+      dfb[i].offL = need;
+      need += packed_size(dfb[i].npad);
+    }
+    if (!p->d_desc_fb && (s = dalloc(p, &p->d_desc_fb, (size_t)p->S)) != PCV_OK) return s;
+    if (need > p->L64fb_cap) {
+      dfree(p, p->d_L64fb, sizeof(double) * (size_t)p->L64fb_cap);
+      p->d_L64fb = nullptr;
+      p->L64fb_cap = 0;
+      if ((s = dalloc(p, &p->d_L64fb, (size_t)need)) != PCV_OK) return s;
+      p->L64fb_cap = need;
+    }
+    HIPCHK(hipMemcpy(p->d_desc_fb, dfb.data(), sizeof(SubsetDesc) * p->S, hipMemcpyHostToDevice));
     int32_t* d_bad = p->d_bad;
     HIPCHK(hipMemcpyAsync(d_bad, bad.data(), sizeof(int32_t) * bad.size(), hipMemcpyHostToDevice, p->stream));
-    s = factor_solve64(p, p->d_desc, p->d_theta, d_bad, (int)bad.size(), p->d_L64, p->d_Inv, p->d_z,
+    s = factor_solve64(p, p->d_desc_fb, p->d_theta, d_bad, (int)bad.size(), p->d_L64fb, p->d_Inv, p->d_z,
                        p->d_alpha, p->d_logdet, p->d_status);
     if (s == PCV_OK) {
       HIPCHK(launch_predict_val(Lc, p->d_val_items, (int)p->val_items.size(), p->d_tx, p->d_ty, p->d_vx,

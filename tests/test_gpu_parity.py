@@ -295,6 +295,42 @@ def test_second_sweep_only_where_residual_above_tol(w_batched_small, graph):
     np.testing.assert_array_equal(batch, single)
 
 
+def test_partial_fallback_matches_fp64_per_subset(w_batched_small):
+    """Subsets re-run in FP64 get their factors in a buffer sized for them
+    alone.  With refine_tol just below the largest first-sweep residual at
+    theta and one sweep, exactly that subset is re-run: its SSPE equals the
+    FP64 path's bit for bit, every other subset keeps its mixed result bit
+    for bit.  At a quarter of the nugget more subsets exceed the same
+    threshold on the same problem (the buffer grows; each re-run subset
+    equals the FP64 path's), and theta again gives the same bits."""
+    w = w_batched_small
+    th = pcv.theta(*w.theta_true)
+    th2 = pcv.theta(w.theta_true[0], w.theta_true[1] / 4)
+    say("[case] partial FP64 fallback")
+    with pcv.Problem.from_workload(w, prec="fp64") as P:
+        l64, r64 = P.eval(th, report=True)
+        l64b, r64b = P.eval(th2, report=True)
+    with pcv.Problem.from_workload(w, prec="mixed", max_refine=1, refine_tol=1.0) as P:
+        l1, r1 = P.eval(th, report=True)
+    m1 = r1["max_rel_residual"]
+    with pcv.Problem.from_workload(w, prec="mixed", max_refine=1, refine_tol=m1 * (1 - 1e-9)) as P:
+        la, ra = P.eval(th, report=True)
+        lb, rb = P.eval(th2, report=True)
+        lc, rc = P.eval(th, report=True)
+    act = r64["per_subset_sspe"] > 0
+    fa = act & (ra["per_subset_iters"] == 0)
+    assert ra["n_fallback_fp64"] == 1 and fa.sum() == 1
+    np.testing.assert_array_equal(ra["per_subset_sspe"][fa], r64["per_subset_sspe"][fa])
+    np.testing.assert_array_equal(ra["per_subset_sspe"][~fa], r1["per_subset_sspe"][~fa])
+    fb = act & (rb["per_subset_iters"] == 0)
+    say(f"   re-run subsets: {int(fa.sum())} at theta, {int(fb.sum())} at a quarter of the nugget")
+    assert rb["n_fallback_fp64"] == fb.sum() > 1
+    np.testing.assert_array_equal(rb["per_subset_sspe"][fb], r64b["per_subset_sspe"][fb])
+    assert abs(lb - l64b) <= TOL_MIXED * l64b
+    assert lc == la
+    np.testing.assert_array_equal(rc["per_subset_sspe"], ra["per_subset_sspe"])
+
+
 @pytest.mark.parametrize("max_refine", [0, 1, 2])
 def test_error_estimate_tracks_fp64(w_batched_small, max_refine):
     """est_rel_err, the loss change one more refinement sweep makes, against
