@@ -537,6 +537,11 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
 
   double ld = 0.0;
   int bad = 0;
+  // rows at or past nlive are padding rows: their covariance entries are 0
+  // and so are their factor entries left of the diagonal (no row of the
+  // subset matrix reaches them), so a wave whose rows all lie there writes
+  // zeros without computing them (the y_T row, n, is live)
+  const int nlive = cyv ? n + 1 : n;
 
   for (int c0 = 0, panel = 0; c0 < npad; c0 += PB, ++panel) {
     const bool two = (SM::NSUB == 2) && (c0 + 128 <= npad);
@@ -556,6 +561,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
       const bool first = (r0 == c0);
       const int wr0 = r0 + WR * w;          // this wave's first row
       const bool wact = wr0 < npad;
+      const bool wlive = wr0 < nlive;
       // In the first chunk, waves 0,1 hold the diagonal block of the first
       // 64 columns, waves 2,3 the second 64 rows of the panel.
       const int wpos = first ? w : 8;     // 8 = an ordinary row block
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
       //      col = c0 + 16 bi + crow(g, v).  Padding points are at infinity, so
       //      their entries are exactly 0; the nugget and the padding's unit
       //      diagonal are set on the diagonal blocks in FP64 (step 3).
-      if (wact) {
+      if (wlive) {
         T xr[NBJ], yr[NBJ];
 #pragma unroll
         for (int bj = 0; bj < NBJ; ++bj) {
@@ -590,6 +596,11 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
 #pragma unroll
           for (int bj = 0; bj < NBJ; ++bj) acc[bi][bj] = acc_t{tv[bj][0], tv[bj][1], tv[bj][2], tv[bj][3]};
         }
+      } else if (wact) {
+#pragma unroll
+        for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBJ; ++bj) acc[bi][bj] = acc_t{};
       }
 
       if constexpr (COOP) {
@@ -647,7 +658,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
         for (int k = 0; k < nst; ++k) {
           const T* Pk = Ps + (k & 1) * SBUF;
           const T* Rk = Pk + PB * LDK;
-          if (wact) {
+          if (wlive) {
             // lane group g takes k = g (KC/4) + q VW + s: NQ 16-byte reads per operand
             // block, VW MFMA steps per read
             constexpr int NQ = KC / (4 * VW);
@@ -749,9 +760,9 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
         __syncthreads();
       }
       if constexpr (SM::TINY) {
-        if (wact && wpos >= 2) trsm_regs_r<T, 0, NBI, NBJ>(acc, invr);
+        if (wlive && wpos >= 2) trsm_regs_r<T, 0, NBI, NBJ>(acc, invr);
       } else {
-        if (wact && wpos >= 2) trsm_regs<T, 0, NBI, NBJ>(acc, InvS[0], lr, g);
+        if (wlive && wpos >= 2) trsm_regs<T, 0, NBI, NBJ>(acc, InvS[0], lr, g);
       }
 
       if constexpr (SM::NSUB == 2) {
@@ -783,7 +794,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
             }
           }
           __syncthreads();
-          if (wact && wpos >= 2) {
+          if (wlive && wpos >= 2) {
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi) {
 #pragma unroll
@@ -823,7 +834,7 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
             }
             __syncthreads();
           }
-          if (wact && wpos >= 4) trsm_regs<T, 4, NBI, NBJ>(acc, InvS[1], lr, g);
+          if (wlive && wpos >= 4) trsm_regs<T, 4, NBI, NBJ>(acc, InvS[1], lr, g);
         }
       }
 
