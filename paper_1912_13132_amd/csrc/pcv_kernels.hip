@@ -263,6 +263,36 @@ __global__ __launch_bounds__(512, (MR <= 8 && sizeof(T) == 4) ? 4 : 2) void k_tr
   }
 }
 
+// Backward-pass update for subsets of at most SNT padded rows (at most
+// SNT / 4 column quads): RS threads share a quad, each summing TB / RS of
+// the block's rows, so that a thread waits for a quarter of the loads; the
+// partial sums go to red[(split * QP + quad) * 4 + u] (QP = SNT / RS).
+template <typename T, int RS>
+__device__ __forceinline__ void bwd_update_split(const T* __restrict__ L, int c0, int tid,
+                                                 const double* __restrict__ xJ, double* __restrict__ red) {
+  typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type q_t;
+  constexpr int QP = SNT / RS, RR = TB / RS;
+  const int q = tid % QP, sp = tid / QP, c = 4 * q;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (c < c0) {
+#pragma unroll 4
+    for (int r = 0; r < RR; ++r) {
+      const int k = sp * RR + r;
+      const q_t v = *reinterpret_cast<const q_t*>(L + packed_rowoff32(c0 + k) + c);
+      const double xr = xJ[k];
+      a0 += (double)v.x * xr;
+      a1 += (double)v.y * xr;
+      a2 += (double)v.z * xr;
+      a3 += (double)v.w * xr;
+    }
+  }
+  double* o = red + 4 * (sp * QP + q);
+  o[0] = a0;
+  o[1] = a1;
+  o[2] = a2;
+  o[3] = a3;
+}
+
 template <typename T, int MQ>
 __global__ __launch_bounds__(512, MQ <= 2 ? 4 : 2) void k_trsv_bwd(const SubsetDesc* __restrict__ desc,
                                                      const int32_t* __restrict__ order,
@@ -311,24 +341,43 @@ __global__ __launch_bounds__(512, MQ <= 2 ? 4 : 2) void k_trsv_bwd(const SubsetD
       if (alpha_accum) alpha_accum[D.offP + c0 + tid] += s;
     }
     __syncthreads();
+    if (MQ <= 2 && npad <= SNT) {
+      // small subset: four threads per column quad; the partial sums reuse
+      // IL (the block's inverse is no longer read) and the quad's owner
+      // (thread q, slot 0) adds them in a fixed order
+      constexpr int RS = 4, QP = SNT / RS;
+      double* red = &IL[0][0];
+      bwd_update_split<T, RS>(L, c0, tid, xJ, red);
+      __syncthreads();
+      if (tid < QP && 4 * tid < c0) {
 #pragma unroll
-    for (int i = 0; i < MQ; ++i) {
-      const int c = 4 * (tid + SNT * i);
-      if (c < c0) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 8
-        for (int r = 0; r < TB; ++r) {
-          const q_t v = *reinterpret_cast<const q_t*>(L + packed_rowoff32(c0 + r) + c);
-          const double xr = xJ[r];
-          a0 += (double)v.x * xr;
-          a1 += (double)v.y * xr;
-          a2 += (double)v.z * xr;
-          a3 += (double)v.w * xr;
+        for (int u = 0; u < 4; ++u) {
+          double a = 0.0;
+#pragma unroll
+          for (int sp = 0; sp < RS; ++sp) a += red[4 * (sp * QP + tid) + u];
+          t[0][u] -= a;
         }
-        t[i][0] -= a0;
-        t[i][1] -= a1;
-        t[i][2] -= a2;
-        t[i][3] -= a3;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < MQ; ++i) {
+        const int c = 4 * (tid + SNT * i);
+        if (c < c0) {
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 8
+          for (int r = 0; r < TB; ++r) {
+            const q_t v = *reinterpret_cast<const q_t*>(L + packed_rowoff32(c0 + r) + c);
+            const double xr = xJ[r];
+            a0 += (double)v.x * xr;
+            a1 += (double)v.y * xr;
+            a2 += (double)v.z * xr;
+            a3 += (double)v.w * xr;
+          }
+          t[i][0] -= a0;
+          t[i][1] -= a1;
+          t[i][2] -= a2;
+          t[i][3] -= a3;
+        }
       }
     }
     __syncthreads();
