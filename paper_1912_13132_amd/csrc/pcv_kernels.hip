@@ -8,6 +8,7 @@
 //   k_residual_*    r = y_T - (Sigma + lambda I) alpha in FP64, the matrix
 //                   regenerated from FP64 coordinates (refinement residual;
 //                   symmetric tiles, fixed-order partial sums)
+//   k_refine_gate   which subsets take a refinement sweep after the first
 //   k_predict_val   kriging predictor eq. (3) at the validation points and
 //                   squared errors of eq. (4), FP64
 //   k_subset_sspe,  per-subset SSPE z_i and the sum of eq. (7) / Algorithm 1
