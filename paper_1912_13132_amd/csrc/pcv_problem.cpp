@@ -62,6 +62,12 @@ void dfree(pcv_problem* p, void* ptr, size_t bytes) {
   p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), ptr), p->allocs.end());
   p->dev_bytes -= bytes;
 }
+// Free what dalloc(p, &ptr, count) allocated (its byte count) and clear ptr.
+template <typename T>
+void dfree_n(pcv_problem* p, T*& ptr, size_t count) {
+  dfree(p, (void*)ptr, std::max<size_t>(count, 1) * sizeof(T));
+  ptr = nullptr;
+}
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -1152,20 +1158,60 @@ namespace {
 
 // Device bytes of one theta slot of the batch workspace.
 size_t batch_slot_bytes(const pcv_problem* p, bool mixed) {
+  // per theta slot: factor, inverses, vectors, partials, predictions, the
+  // per-subset arrays and descriptors, and the plans' item lists
   return (size_t)p->nL * (mixed ? 4 : 8) + (size_t)p->nInv * 8 + (size_t)p->nP * 8 * 6 +
-         (size_t)p->nPC * 8 + (size_t)p->nnzV * 8 * 2 + (size_t)p->S * (8 * 4 + 4 * 3 + sizeof(SubsetDesc)) + 64;
+         (size_t)p->nPC * 8 + (size_t)p->nnzV * 8 * 2 + (size_t)p->S * (8 * 4 + 4 * 3 + sizeof(SubsetDesc)) +
+         (size_t)p->S * 4 + (p->row_items_eval.size() * 2 + p->val_items.size()) * sizeof(int2) + 64;
 }
 
+// The multi-theta workspace's buffers (those allocated so far), freed.
+void free_batch(pcv_problem* p, int B, bool mixed) {
+  pcv_batch& b = p->batch;
+  const size_t S = (size_t)p->S, Bs = (size_t)B;
+  dfree_n(p, b.d_desc, Bs * S);
+  if (mixed) {
+    float* L = (float*)b.d_L;
+    dfree_n(p, L, Bs * p->nL);
+  } else {
+    double* L = (double*)b.d_L;
+    dfree_n(p, L, Bs * p->nL);
+  }
+  b.d_L = nullptr;
+  dfree_n(p, b.d_Inv, Bs * p->nInv);
+  for (double** q : {&b.d_z, &b.d_x, &b.d_alpha, &b.d_r, &b.d_rrow}) dfree_n(p, *q, Bs * p->nP);
+  dfree_n(p, b.d_pcol, Bs * std::max<int64_t>(p->nPC, 1));
+  dfree_n(p, b.d_yhat, Bs * std::max<int64_t>(p->nnzV, 1));
+  dfree_n(p, b.d_err, Bs * std::max<int64_t>(p->nnzV, 1));
+  for (double** q : {&b.d_rhs2, &b.d_logdet, &b.d_sspe, &b.d_quad}) dfree_n(p, *q, Bs * S);
+  for (int32_t** q : {&b.d_status, &b.d_gate, &b.d_nsweep}) dfree_n(p, *q, Bs * S);
+  dfree_n(p, b.d_total, Bs);
+  dfree_n(p, b.d_nbad, Bs);
+  dfree_n(p, b.d_theta, Bs);
+  if (b.h_theta) (void)hipHostFree(b.h_theta);
+  if (b.h_total) (void)hipHostFree(b.h_total);
+  if (b.h_nbad) (void)hipHostFree(b.h_nbad);
+  b.h_theta = nullptr;
+  b.h_total = nullptr;
+  b.h_nbad = nullptr;
+  b.B = 0;
+}
+
+// Allocate the workspace for B theta slots; on failure nothing of it is
+// kept (so that a caller can fall back to one theta at a time).
 pcv_status ensure_batch(pcv_problem* p, int B, bool mixed) {
   pcv_batch& b = p->batch;
   if (b.B >= B) return PCV_OK;
   if (b.B > 0) return fail(PCV_ERR_STATE, "batch workspace already sized");
   const int S = p->S;
   pcv_status s;
-#define TRYB(x)              \
-  do {                       \
-    s = (x);                 \
-    if (s != PCV_OK) return s; \
+#define TRYB(x)                  \
+  do {                           \
+    s = (x);                     \
+    if (s != PCV_OK) {           \
+      free_batch(p, B, mixed);   \
+      return s;                  \
+    }                            \
   } while (0)
   std::vector<SubsetDesc> db((size_t)B * S);
   for (int t = 0; t < B; ++t)
@@ -1202,9 +1248,15 @@ pcv_status ensure_batch(pcv_problem* p, int B, bool mixed) {
   TRYB(dalloc(p, &b.d_nbad, (size_t)B));
   TRYB(dalloc(p, &b.d_theta, (size_t)B));
 #undef TRYB
-  HIPCHK(hipHostMalloc((void**)&b.h_theta, sizeof(ThetaDev) * B, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc((void**)&b.h_total, sizeof(double) * B, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc((void**)&b.h_nbad, sizeof(int32_t) * B, hipHostMallocDefault));
+  hipError_t e = hipHostMalloc((void**)&b.h_theta, sizeof(ThetaDev) * B, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_total, sizeof(double) * B, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_nbad, sizeof(int32_t) * B, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    free_batch(p, B, mixed);
+    return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,
+                std::string("batch host buffers: ") + hipGetErrorString(e));
+  }
   b.B = B;
   return PCV_OK;
 }
@@ -1246,10 +1298,16 @@ pcv_status batch_plan(pcv_problem* p, int nb, pcv_batch_plan** out) {
   std::vector<int2> tiles = rows;
   std::stable_sort(tiles.begin(), tiles.end(), [](const int2& a, const int2& c) { return a.y > c.y; });
   pcv_status s;
-  if ((s = upload(p, &pl->d_order, order)) != PCV_OK) return s;
-  if ((s = upload(p, &pl->d_row_items, rows)) != PCV_OK) return s;
-  if ((s = upload(p, &pl->d_tile_items, tiles)) != PCV_OK) return s;
-  if ((s = upload(p, &pl->d_val_items, vals)) != PCV_OK) return s;
+  if ((s = upload(p, &pl->d_order, order)) != PCV_OK || (s = upload(p, &pl->d_row_items, rows)) != PCV_OK ||
+      (s = upload(p, &pl->d_tile_items, tiles)) != PCV_OK || (s = upload(p, &pl->d_val_items, vals)) != PCV_OK) {
+    // nothing of a plan that did not fit is kept
+    dfree_n(p, pl->d_order, order.size());
+    dfree_n(p, pl->d_row_items, rows.size());
+    dfree_n(p, pl->d_tile_items, tiles.size());
+    dfree_n(p, pl->d_val_items, vals.size());
+    *pl = pcv_batch_plan{};
+    return s;
+  }
   pl->n_order = (int)order.size();
   pl->n_row = (int)rows.size();
   pl->n_tile = (int)tiles.size();
@@ -1359,8 +1417,9 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
   if (p->opt.mem_cap_bytes) budget = p->opt.mem_cap_bytes > p->dev_bytes ? p->opt.mem_cap_bytes - p->dev_bytes : 0;
   int B = (int)std::min<size_t>({(size_t)64, (size_t)K, budget / std::max<size_t>(slot, 1)});
   if (p->batch.B > 0) B = std::min(std::max(B, 1), p->batch.B);
-  if (K < 2 || B < 2 || p->n_active == 0) {
-    for (int32_t k = 0; k < K; ++k) {
+  // theta values k0.. one at a time
+  auto singles = [&](int32_t k0) -> pcv_status {
+    for (int32_t k = k0; k < K; ++k) {
       pcv_eval_report r1;
       std::memset(&r1, 0, sizeof(r1));
       r1.per_subset_sspe = zs ? zs + (size_t)k * p->S : nullptr;
@@ -1380,8 +1439,12 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
     }
     if (rep) rep->seconds = now_s() - t0;
     return PCV_OK;
-  }
+  };
+  if (K < 2 || B < 2 || p->n_active == 0) return singles(0);
+  // a workspace or plan that does not fit the memory cap (or the device)
+  // leaves nothing behind, and the theta values go one at a time
   pcv_status s = ensure_batch(p, B, mixed);
+  if (s == PCV_ERR_OOM) return singles(0);
   if (s != PCV_OK) return s;
   pcv_batch& b = p->batch;
   for (int32_t g0 = 0; g0 < K; g0 += B) {
@@ -1397,7 +1460,8 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
       h.sigma2 = th.sigma2;
     }
     pcv_batch_plan* pl = nullptr;
-    if ((s = batch_plan(p, nb, &pl)) != PCV_OK) return s;
+    if ((s = batch_plan(p, nb, &pl)) == PCV_ERR_OOM) return singles(g0);
+    if (s != PCV_OK) return s;
     const bool ev = p->events && rep;
     if (p->opt.graph && !ev && !p->served) {
       if (!pl->graph) {

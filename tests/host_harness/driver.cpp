@@ -26,6 +26,7 @@ int64_t stub_live_pinned();
 int64_t stub_live_streams();
 int64_t stub_live_events();
 void stub_report(const char* tag);
+void stub_fail_malloc_after(int64_t n);
 }
 
 #define CHECK(x)                                                                                   \
@@ -210,6 +211,42 @@ void oom(const Data& d) {
   std::printf("oom: rejected with nothing left behind\n");
 }
 
+// A device allocation that fails at every point of a multi-theta call:
+// the call returns PCV_OK (the workspace or plan that did not fit is given
+// up, the theta values go one at a time) or PCV_ERR_OOM (a single
+// evaluation could not allocate), the problem's byte count matches what it
+// holds, and the next call without the failure builds the workspace.
+void oom_batch(const Data& d) {
+  const Live base = Live::now();
+  std::vector<pcv_theta> ths;
+  for (int k = 0; k < 9; ++k) ths.push_back(th(0.2 + 0.01 * k, 0.05 + 0.005 * k));
+  std::vector<double> losses(9);
+  int ok = 0, oom = 0, dropped = 0;
+  for (int64_t k = 0; k < 60; ++k) {
+    pcv_options o;
+    pcv_default_options(&o);
+    pcv_problem* p = create(d, o);
+    evals(p, 1);
+    const int64_t a0 = stub_live_allocations();
+    size_t b0 = 0;
+    CHECK(pcv_problem_info(p, nullptr, nullptr, nullptr, &b0));
+    stub_fail_malloc_after(k);
+    const pcv_status s = pcv_eval_batch(p, 9, ths.data(), losses.data());
+    stub_fail_malloc_after(-1);
+    EXPECT(s == PCV_OK || s == PCV_ERR_OOM);
+    if (s == PCV_OK) ++ok; else ++oom;
+    size_t b1 = 0;
+    CHECK(pcv_problem_info(p, nullptr, nullptr, nullptr, &b1));
+    // nothing was allocated, or the workspace was kept (then more bytes)
+    EXPECT((stub_live_allocations() == a0) == (b1 == b0));
+    if (b1 == b0) ++dropped;
+    CHECK(pcv_eval_batch(p, 9, ths.data(), losses.data()));
+    CHECK(pcv_problem_destroy(p));
+  }
+  EXPECT(Live::now() == base);
+  std::printf("oom_batch: %d calls ok, %d out of memory, %d gave the workspace up\n", ok, oom, dropped);
+}
+
 // The tuner's cycle on three problems in one process (tune, reuse of the
 // cache on an identical problem, a new problem shape), with evaluations,
 // batches and a server between, then tuning of a problem whose configuration
@@ -286,6 +323,7 @@ int main(int argc, char** argv) {
     stub_report("sequence");
   } else if (sc == "oom") {
     oom(d);
+    oom_batch(make_data(40, 3));
   } else if (sc == "tune_after_serving") {
     tune_after_serving(make_data(290, 2));
     stub_report("tune_after_serving");

@@ -63,6 +63,9 @@ namespace {
 // The registries are never destroyed (no static destructors run before the
 // leak check at exit), so destroyed handles kept in g_dead stay reachable.
 std::recursive_mutex& g_mu = *new std::recursive_mutex;
+// Failure injection: with g_fail_after >= 0, that many more hipMalloc calls
+// succeed and the next ones report hipErrorOutOfMemory until it is reset.
+int64_t g_fail_after = -1;
 struct Alloc {
   size_t size;
   bool pinned;
@@ -149,6 +152,11 @@ void enqueue(hipStream_t s, const char* what, std::function<void()> op) {
 
 extern "C" {
 
+void stub_fail_malloc_after(int64_t n) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_fail_after = n;
+}
+
 int64_t stub_live_allocations() {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   int64_t n = 0;
@@ -183,6 +191,11 @@ void stub_report(const char* tag) {
 hipError_t hipMalloc(void** ptr, size_t size) {
   no_capture("hipMalloc");
   std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (g_fail_after == 0) {
+    *ptr = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  if (g_fail_after > 0) --g_fail_after;
   void* p = std::calloc(size ? size : 1, 1);
   if (!p) return hipErrorOutOfMemory;
   g_live[(uintptr_t)p] = Alloc{size, false};

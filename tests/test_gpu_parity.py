@@ -517,3 +517,32 @@ def test_two_stream_schedule(prec, tol):
         np.testing.assert_array_equal(out[name][1]["per_subset_sspe"], out["graph"][1]["per_subset_sspe"])
         np.testing.assert_array_equal(out[name][1]["per_subset_logdet"], out["graph"][1]["per_subset_logdet"])
     assert _rel(out["graph"][0], ref["sspe"]) <= tol
+
+
+# ----------------------------------------------------------- memory cap ---
+def test_memory_cap_refuses_and_bounds_the_batch_workspace(w_plain):
+    """mem_cap_bytes below what the problem needs: creation fails with
+    PCV_ERR_OOM (and a later problem on the device works).  A cap that holds
+    the problem and its factor but not the multi-theta workspace: the
+    batched call evaluates theta by theta, bit for bit the same losses; a
+    cap that also holds a small workspace gives the same bits."""
+    th = pcv.theta(0.1, 0.05)
+    ths = [pcv.theta(*t) for t in W.theta_grid(w_plain.theta_true, 3)]
+    say("[case] memory cap")
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        l_ref = P.eval(th)
+        need = P.info()["device_bytes"]
+        b_ref = P.eval_batch(ths)
+        need_batch = P.info()["device_bytes"]
+    assert need_batch > need
+    with pytest.raises(pcv.PcvError) as e:
+        pcv.Problem.from_workload(w_plain, prec="mixed", mem_cap=need // 4)
+    assert e.value.status == 2
+    with pcv.Problem.from_workload(w_plain, prec="mixed", mem_cap=need + (1 << 20)) as P:
+        assert P.eval(th) == l_ref
+        np.testing.assert_array_equal(P.eval_batch(ths), b_ref)
+        assert P.info()["device_bytes"] <= need + (1 << 20)
+    slot = (need_batch - need) // len(ths)
+    with pcv.Problem.from_workload(w_plain, prec="mixed", mem_cap=need + 3 * slot + (1 << 20)) as P:
+        assert P.eval(th) == l_ref
+        np.testing.assert_array_equal(P.eval_batch(ths), b_ref)

@@ -10,7 +10,9 @@ stand-in of the HIP runtime and of the kernel launchers
             eager / profiled / forced-fallback / busy-device variants, three
             times on fresh problems;
   oom       a memory cap below the problem's need: PCV_ERR_OOM with nothing
-            left behind;
+            left behind; a device allocation failing at each point of a
+            multi-theta call: the workspace or plan that did not fit is
+            given up and the theta values go one at a time;
   tune      the autotuner on three problems of two shapes in both
             precisions: timing, the cache file (written, then reused for the
             identical problem), evaluations, batches and a server after
@@ -21,6 +23,7 @@ every live allocation (also when a captured graph is replayed), a call the
 capture mode forbids, or resources left alive after every problem is gone.
 No GPU is used."""
 import os
+import re
 import shutil
 import subprocess
 from concurrent.futures import ThreadPoolExecutor
@@ -73,7 +76,13 @@ def test_call_sequences_clean_under_sanitizers(driver):
 
 
 def test_memory_cap_rejects_without_side_effects(driver):
-    assert "nothing left behind" in _run(driver, "oom")
+    out = _run(driver, "oom")
+    assert "nothing left behind" in out
+    # a device allocation failing at every point of a multi-theta call
+    # (the single evaluations need no new device memory here, so every call
+    # completes; early failures give the workspace up, late ones keep it)
+    m = re.search(r"oom_batch: (\d+) calls ok, (\d+) out of memory, (\d+) gave the workspace up", out)
+    assert m and int(m.group(1)) == 60 and 0 < int(m.group(3)) < 60, out[-2000:]
 
 
 def test_tuner_cycle_clean_under_sanitizers(driver):
