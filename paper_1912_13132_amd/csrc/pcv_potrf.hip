@@ -483,7 +483,6 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
   constexpr int PB = SM::PB, KC = SM::KC, VW = SM::VW, LDK = SM::LDK, LDI = SM::LDI;
   constexpr int NBI = PB / 16;                    // accumulator block rows (panel columns)
   constexpr int NVEC = (PB + RCH) * (KC / VW);    // 16-byte vectors per stage
-  constexpr int VPT = (NVEC + NT - 1) / NT;       // per thread
   constexpr int VPR = KC / VW;                    // vectors per row (4)
   typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
 
@@ -611,28 +610,34 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
       }
 
       // ---- 2. update: C^T -= L[c0:c0+PB, 0:c0] L[rows, 0:c0]^T
-      //      Two LDS stage buffers: while the MFMAs consume stage k, stage k+1 is
-      //      stored from registers and stage k+2 is loaded; one barrier per stage.
+      //      Two LDS stage buffers and one barrier per stage, placed between
+      //      the stage's two halves (q = 0, 1) of operand columns.  First half
+      //      of stage k: the MFMAs on the q = 0 operands (read before) while
+      //      the q = 1 operands are read, stage k + 1 is stored into the other
+      //      buffer and stage k + 2 is requested from memory.  Barrier: stage
+      //      k + 1 complete.  Second half: the MFMAs on the q = 1 operands
+      //      while the q = 0 operands of stage k + 1 are read.  No wave waits
+      //      on LDS before its MFMAs, and the stores drain behind them.
       if (c0 > 0) {
-        // staging map: vector vi = tid + NT s -> (row vi / VPR, 16-byte column slot vi % VPR);
-        // rows [0, PB) are panel rows (stored negated), the rest chunk rows
+        // staging map: vector vi = tid + NT s -> (row vi / VPR, 16-byte column
+        // slot vi % VPR); rows [0, PB) are panel rows (stored negated), the
+        // rest chunk rows.  Rows past npad read row npad - 1 instead: they
+        // only feed accumulators that are never used (chunk rows of waves
+        // past the matrix, the second half of a half-width last panel).
+        static_assert(NVEC % NT == 0 && (PB * VPR) % NT == 0, "stage rows split evenly");
+        constexpr int VPT = NVEC / NT;
         int goff[VPT];
-        bool gok[VPT];
 #pragma unroll
         for (int s = 0; s < VPT; ++s) {
           const int vi = tid + NT * s;
           const int row = vi / VPR, cv = vi % VPR;
           const int grow = row < PB ? c0 + row : r0 + (row - PB);
-          gok[s] = (vi < NVEC) & (grow < npad);
-          goff[s] = packed_rowoff32(gok[s] ? grow : 0) + cv * VW;
+          goff[s] = packed_rowoff32(min(grow, npad - 1)) + cv * VW;
         }
         vec_t st[VPT];
         auto gload = [&](int k0) {
 #pragma unroll
-          for (int s = 0; s < VPT; ++s) {
-            const vec_t v = *reinterpret_cast<const vec_t*>(L + goff[s] + k0);
-            st[s] = gok[s] ? v : vec_t{};
-          }
+          for (int s = 0; s < VPT; ++s) st[s] = *reinterpret_cast<const vec_t*>(L + goff[s] + k0);
         };
         auto lstore = [&](T* buf) {
 #pragma unroll
@@ -640,55 +645,102 @@ __global__ __launch_bounds__(NTH, 2) void k_potrf(const SubsetDesc* __restrict__
             const int vi = tid + NT * s;
             const int row = vi / VPR, cv = vi % VPR;
             vec_t v = st[s];
-            if (row < PB) {
+            if (NT * s < PB * VPR) {  // a panel row
               T* p = reinterpret_cast<T*>(&v);
 #pragma unroll
               for (int e = 0; e < VW; ++e) p[e] = -p[e];
             }
-            if (vi < NVEC) *reinterpret_cast<vec_t*>(buf + row * LDK + cv * VW) = v;
+            *reinterpret_cast<vec_t*>(buf + row * LDK + cv * VW) = v;
           }
         };
+        // lane group g takes k = g (KC/4) + q VW + s: one 16-byte read per
+        // operand block and half, VW MFMA steps per read
+        static_assert(KC == 8 * VW, "two operand halves per stage");
         constexpr int SBUF = (PB + RCH) * LDK;  // elements per stage buffer
+        vec_t pa0[NBI], rb0[NBJ], pa1[NBI], rb1[NBJ];
+        // (the loop is free of branches around memory operations, so that
+        // the waits the compiler places before each half's MFMAs cover only
+        // the operands that half uses: the last stage stores and loads a
+        // spare stage)
+        auto rd = [&](const T* buf, int q, vec_t (&pa)[NBI], vec_t (&rb)[NBJ]) {
+          const T* Rk = buf + PB * LDK;
+#pragma unroll
+          for (int bj = 0; bj < NBJ; ++bj)
+            rb[bj] = *reinterpret_cast<const vec_t*>(Rk + (WR * w + 16 * bj + lr) * LDK + g * (KC / 4) + q * VW);
+#pragma unroll
+          for (int bi = 0; bi < NBI; ++bi)
+            pa[bi] = *reinterpret_cast<const vec_t*>(buf + (16 * bi + lr) * LDK + g * (KC / 4) + q * VW);
+        };
+        auto mm = [&](const vec_t (&pa)[NBI], const vec_t (&rb)[NBJ]) {
+#pragma unroll
+          for (int h = 0; h < NBI; h += 4)
+#pragma unroll
+            for (int s = 0; s < VW; ++s)
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int bj = 0; bj < NBJ; ++bj)
+                  acc[h + b][bj] = Cfg<T>::mma(reinterpret_cast<const T*>(&pa[h + b])[s],
+                                               reinterpret_cast<const T*>(&rb[bj])[s], acc[h + b][bj]);
+        };
+        // Instruction order inside each half (the two waves of a SIMD run in
+        // step, so memory instructions issued between MFMAs are hidden behind
+        // the other wave's MFMAs): one LDS read after each of the first MFMAs,
+        // then the LDS stores and the memory loads between pairs of MFMAs.
+        // The scheduling fences keep the halves apart.
+        constexpr int NRD = NBI + NBJ;  // LDS reads per half
+        auto order_first_half = [] {
+#pragma unroll
+          for (int i = 0; i < NRD; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+          }
+#pragma unroll
+          for (int i = 0; i < VPT; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // memory read
+          }
+        };
+        auto order_second_half = [] {
+#pragma unroll
+          for (int i = 0; i < NRD; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
+        };
         const int nst = c0 / KC;
         gload(0);
         lds_barrier();  // LDS free (previous phase done with smem_u)
         lstore(Ps);
         if (nst > 1) gload(KC);
         lds_barrier();
-        for (int k = 0; k < nst; ++k) {
-          const T* Pk = Ps + (k & 1) * SBUF;
-          const T* Rk = Pk + PB * LDK;
-          if (wlive) {
-            // lane group g takes k = g (KC/4) + q VW + s: NQ 16-byte reads per operand
-            // block, VW MFMA steps per read
-            constexpr int NQ = KC / (4 * VW);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-              vec_t rb[NBJ];
-#pragma unroll
-              for (int bj = 0; bj < NBJ; ++bj)
-                rb[bj] = *reinterpret_cast<const vec_t*>(Rk + (WR * w + 16 * bj + lr) * LDK + g * (KC / 4) +
-                                                         q * VW);
-#pragma unroll
-              for (int h = 0; h < NBI; h += 4) {
-                vec_t pa[4];
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                  pa[b] = *reinterpret_cast<const vec_t*>(Pk + (16 * (h + b) + lr) * LDK + g * (KC / 4) + q * VW);
-#pragma unroll
-                for (int s = 0; s < VW; ++s)
-#pragma unroll
-                  for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int bj = 0; bj < NBJ; ++bj)
-                      acc[h + b][bj] = Cfg<T>::mma(reinterpret_cast<const T*>(&pa[b])[s],
-                                                   reinterpret_cast<const T*>(&rb[bj])[s], acc[h + b][bj]);
-              }
-            }
+        if (wlive) {
+          rd(Ps, 0, pa0, rb0);
+          for (int k = 0; k < nst; ++k) {
+            const T* Bk = Ps + (k & 1) * SBUF;
+            T* Bn = Ps + ((k + 1) & 1) * SBUF;
+            rd(Bk, 1, pa1, rb1);
+            lstore(Bn);
+            gload(min(k + 2, nst - 1) * KC);
+            mm(pa0, rb0);
+            order_first_half();
+            __builtin_amdgcn_sched_barrier(0);
+            lds_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            rd(Bn, 0, pa0, rb0);
+            mm(pa1, rb1);
+            order_second_half();
+            __builtin_amdgcn_sched_barrier(0);
           }
-          if (k + 1 < nst) lstore(Ps + ((k + 1) & 1) * SBUF);
-          if (k + 2 < nst) gload((k + 2) * KC);
-          lds_barrier();
+        } else {
+          // waves without live rows: their share of the staging only
+          for (int k = 0; k < nst; ++k) {
+            lstore(Ps + ((k + 1) & 1) * SBUF);
+            gload(min(k + 2, nst - 1) * KC);
+            lds_barrier();
+          }
         }
       }
 
