@@ -152,13 +152,10 @@ struct SVec<double> {
   static constexpr int W = 2;
 };
 
-// One 64 x 64 inverse diagonal block into LDS.  Its upper part is stored as
-// zeros, so only the pairs that reach the lower part are read (5/8 of the
-// block's cache lines).
 __device__ __forceinline__ void stage_inv(double (*IL)[65], const double* __restrict__ Iblk, int tid) {
   for (int e = tid; e < 2048; e += SNT) {
+    const double2 v = reinterpret_cast<const double2*>(Iblk)[e];
     const int i = (2 * e) >> 6, j = (2 * e) & 63;
-    const double2 v = j <= i ? reinterpret_cast<const double2*>(Iblk)[e] : double2{0.0, 0.0};
     IL[i][j] = v.x;
     IL[i][j + 1] = v.y;
   }
