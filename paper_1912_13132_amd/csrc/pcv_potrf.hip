@@ -16,7 +16,9 @@
 //      block is moved to FP64;
 //   2. C^T -= L_J L_R^T over all previous columns, on MFMA from 128-byte row
 //      segments staged through two LDS buffers (loads for stage k+2 in flight
-//      while stage k is consumed; conflict-free 16-byte operand reads);
+//      while stage k is consumed; conflict-free 16-byte operand reads; one
+//      barrier per stage, between its two operand halves, so that each
+//      half's operands are read while the other half's MFMAs run);
 //   3. the diagonal 64 x 64 blocks of the panel are factored in FP64 in LDS
 //      (blocked in 16 x 16 tiles), inverted in FP64 into the free upper half
 //      of the same array, and the inverse is kept in LDS;
