@@ -33,9 +33,11 @@ using pcv::fail;
 #define HIPCHK(x)                                                                          \
   do {                                                                                     \
     hipError_t e_ = (x);                                                                   \
-    if (e_ != hipSuccess)                                                                  \
+    if (e_ != hipSuccess) {                                                                \
+      (void)hipGetLastError(); /* reported here, not again at a later launch */            \
       return fail(e_ == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,                \
                   std::string(#x) + ": " + hipGetErrorString(e_));                         \
+    }                                                                                      \
   } while (0)
 
 namespace {
@@ -145,7 +147,10 @@ pcv_status pcv_selftest_math(int64_t n, const double* t, const double* x, double
   const size_t bytes = sizeof(double) * (size_t)n;
   double* d = nullptr;
   hipError_t err = hipMalloc((void**)&d, 4 * bytes);
-  if (err != hipSuccess) return fail(PCV_ERR_OOM, hipGetErrorString(err));
+  if (err != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PCV_ERR_OOM, hipGetErrorString(err));
+  }
   if (err == hipSuccess) err = hipMemcpy(d, t, bytes, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(d + n, x, bytes, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = pcv::launch_math_check(nullptr, n, d, d + n, d + 2 * n, d + 3 * n);

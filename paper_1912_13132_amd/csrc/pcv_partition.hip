@@ -42,9 +42,11 @@ struct DevBuf {
 #define PCHK(x)                                                                                    \
   do {                                                                                             \
     hipError_t e_ = (x);                                                                           \
-    if (e_ != hipSuccess)                                                                          \
+    if (e_ != hipSuccess) {                                                                        \
+      (void)hipGetLastError(); /* reported here, not again at a later launch */                    \
       return fail(e_ == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,                        \
                   std::string("partition: ") + #x + ": " + hipGetErrorString(e_));                  \
+    }                                                                                              \
   } while (0)
 
 template <typename T>

@@ -20,9 +20,11 @@ using pcv::TB;
 #define HIPCHK(x)                                                                          \
   do {                                                                                     \
     hipError_t e_ = (x);                                                                   \
-    if (e_ != hipSuccess)                                                                  \
+    if (e_ != hipSuccess) {                                                                \
+      (void)hipGetLastError(); /* reported here, not again at a later launch */            \
       return fail(e_ == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,                \
                   std::string(#x) + ": " + hipGetErrorString(e_));                         \
+    }                                                                                      \
   } while (0)
 
 namespace pcv {
@@ -1602,8 +1604,10 @@ pcv_status gls_impl(pcv_problem* p, int32_t ncov, const double* X, double* beta,
   if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), d_st, sizeof(int32_t) * p->S, hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   for (void* b : {(void*)d_X, (void*)d_W, (void*)d_beta, (void*)d_st}) (void)hipFree(b);
-  if (e != hipSuccess)
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // a failed allocation must not surface at a later launch
     return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE, std::string("gls: ") + hipGetErrorString(e));
+  }
   // subsets without training points have no estimate
   std::vector<char> has(p->S, 0);
   for (int32_t i : p->order_all) has[i] = 1;
@@ -1658,9 +1662,11 @@ pcv_status predict_impl(pcv_problem* p, int64_t q, const double* ql, double* mea
   for (void* b : {(void*)d_qx, (void*)d_qy, (void*)d_mean, (void*)d_var, (void*)d_W, (void*)d_qorig,
                   (void*)d_qflag, (void*)d_items})
     (void)hipFree(b);
-  if (e != hipSuccess)
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // a failed allocation must not surface at a later launch
     return fail(e == hipErrorOutOfMemory ? PCV_ERR_OOM : PCV_ERR_DEVICE,
                 std::string("predict: ") + hipGetErrorString(e));
+  }
   return PCV_OK;
 }
 

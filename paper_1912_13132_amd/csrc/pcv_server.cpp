@@ -411,10 +411,11 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
   // Per slot: 40 bytes per query (coordinates, mean, variance, index, flags)
   // and, per item of up to KRIGE_Q queries, a KrigeItem and an
   // npad x KRIGE_Q variance panel.
-  const size_t per_slot = mem_budget / (size_t)n_slots;
+  // (signed: a budget below the query buffers leaves no room for items)
+  const int64_t per_slot = (int64_t)std::min<size_t>(mem_budget / (size_t)n_slots, (size_t)1 << 60);
   const int64_t w_item = (int64_t)std::max(p->max_npad, (int32_t)pcv::TB) * KRIGE_Q;
-  s->q_cap = std::max<int64_t>(64, std::min<int64_t>(1 << 20, (int64_t)(per_slot / 4) / 40));
-  s->w_cap = (int64_t)((per_slot - (size_t)s->q_cap * 40) / 8);
+  s->q_cap = std::max<int64_t>(64, std::min<int64_t>(1 << 20, per_slot / 4 / 40));
+  s->w_cap = std::max<int64_t>(0, per_slot - s->q_cap * 40) / 8;
   s->item_cap = s->w_cap / w_item;
   if (s->item_cap < 1) {
     delete s;
@@ -452,6 +453,7 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
     s->ws_bytes += (size_t)Q * 40 + sizeof(KrigeItem) * I + 8 * (size_t)s->w_cap;
   }
   if (e != hipSuccess) {
+    (void)hipGetLastError();  // a failed allocation must not surface at a later launch
     free_slots_mem(s);
     delete s;
     (void)set_served(p, false);

@@ -247,6 +247,53 @@ void oom_batch(const Data& d) {
   std::printf("oom_batch: %d calls ok, %d out of memory, %d gave the workspace up\n", ok, oom, dropped);
 }
 
+// Server creation failing at each device or pinned allocation in turn:
+// PCV_ERR_OOM with the problem back as it was (its stream, not served, no
+// resources left behind); a workspace no device holds fails the same way;
+// the next creation works and serves.
+void oom_server(const Data& d) {
+  const Live base = Live::now();
+  pcv_options o;
+  pcv_default_options(&o);
+  pcv_problem* p = create(d, o);
+  pcv_theta t = th(0.2, 0.05);
+  CHECK(pcv_factor(p, &t));
+  evals(p, 1);
+  const Live before = Live::now();
+  int ok = 0, oom = 0;
+  for (int64_t k = 0; k < 60; ++k) {
+    pcv_server* srv = nullptr;
+    stub_fail_malloc_after(k);
+    const pcv_status s = pcv_server_create(&srv, p, (size_t)64 << 20, 4);
+    stub_fail_malloc_after(-1);
+    EXPECT(s == PCV_OK || s == PCV_ERR_OOM);
+    if (s == PCV_OK) {
+      ++ok;
+      CHECK(pcv_server_destroy(srv));
+    } else {
+      ++oom;
+      EXPECT(srv == nullptr);
+    }
+    evals(p, 1);  // the problem still evaluates on its own stream
+    EXPECT(Live::now() == before);
+  }
+  pcv_server* srv = nullptr;
+  for (size_t b : {(size_t)1, (size_t)1024, (size_t)7000, (size_t)3 * 64 * 40})
+    EXPECT(pcv_server_create(&srv, p, b, 4) == PCV_ERR_INVALID);  // below one kriging item per slot
+  EXPECT(pcv_server_create(&srv, p, (size_t)1 << 50, 4) == PCV_ERR_OOM);
+  evals(p, 1);
+  EXPECT(Live::now() == before);
+  CHECK(pcv_server_create(&srv, p, (size_t)64 << 20, 4));
+  std::vector<double> q = {0.3, 0.4, 0.7, 0.2}, out(4);
+  pcv_ticket tk;
+  CHECK(pcv_server_submit_predict(srv, 2, q.data(), out.data(), out.data() + 2, 0, &tk));
+  CHECK(pcv_server_wait(srv, tk, -1.0));
+  CHECK(pcv_server_destroy(srv));
+  CHECK(pcv_problem_destroy(p));
+  EXPECT(Live::now() == base);
+  std::printf("oom_server: %d created, %d out of memory\n", ok, oom);
+}
+
 // The tuner's cycle on three problems in one process (tune, reuse of the
 // cache on an identical problem, a new problem shape), with evaluations,
 // batches and a server between, then tuning of a problem whose configuration
@@ -324,6 +371,7 @@ int main(int argc, char** argv) {
   } else if (sc == "oom") {
     oom(d);
     oom_batch(make_data(40, 3));
+    oom_server(make_data(40, 4));
   } else if (sc == "tune_after_serving") {
     tune_after_serving(make_data(290, 2));
     stub_report("tune_after_serving");

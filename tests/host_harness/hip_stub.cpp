@@ -66,6 +66,10 @@ std::recursive_mutex& g_mu = *new std::recursive_mutex;
 // Failure injection: with g_fail_after >= 0, that many more hipMalloc calls
 // succeed and the next ones report hipErrorOutOfMemory until it is reset.
 int64_t g_fail_after = -1;
+// The runtime's per-thread last error: a failed call sets it, hipGetLastError
+// returns and clears it (the launch wrappers return it after each launch).
+thread_local hipError_t g_last_error = hipSuccess;
+constexpr size_t kStubMaxAlloc = (size_t)1 << 40;
 struct Alloc {
   size_t size;
   bool pinned;
@@ -190,10 +194,14 @@ void stub_report(const char* tag) {
 
 hipError_t hipMalloc(void** ptr, size_t size) {
   no_capture("hipMalloc");
+  if (size > kStubMaxAlloc) {  // more than any device or host holds
+    *ptr = nullptr;
+    return g_last_error = hipErrorOutOfMemory;
+  }
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   if (g_fail_after == 0) {
     *ptr = nullptr;
-    return hipErrorOutOfMemory;
+    return g_last_error = hipErrorOutOfMemory;
   }
   if (g_fail_after > 0) --g_fail_after;
   void* p = std::calloc(size ? size : 1, 1);
@@ -214,7 +222,16 @@ hipError_t hipFree(void* ptr) {
 }
 hipError_t hipHostMalloc(void** ptr, size_t size, unsigned int) {
   no_capture("hipHostMalloc");
+  if (size > kStubMaxAlloc) {  // more than any device or host holds
+    *ptr = nullptr;
+    return g_last_error = hipErrorOutOfMemory;
+  }
   std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (g_fail_after == 0) {
+    *ptr = nullptr;
+    return g_last_error = hipErrorOutOfMemory;
+  }
+  if (g_fail_after > 0) --g_fail_after;
   void* p = std::calloc(size ? size : 1, 1);
   if (!p) return hipErrorOutOfMemory;
   g_live[(uintptr_t)p] = Alloc{size, true};
@@ -445,7 +462,11 @@ hipError_t hipRuntimeGetVersion(int* v) {
   *v = 1;
   return hipSuccess;
 }
-hipError_t hipGetLastError(void) { return hipSuccess; }
+hipError_t hipGetLastError(void) {
+  const hipError_t e = g_last_error;
+  g_last_error = hipSuccess;
+  return e;
+}
 const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "hipSuccess" : "hip-stub error"; }
 hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
@@ -503,7 +524,7 @@ hipError_t launch_potrf_f32(const Launch& L, const int32_t* order, int n, int, c
   if (cv && c.n_blocks > 0 && (!c.subsets || c.n_subsets <= 0)) return hipErrorInvalidValue;
   launched("potrf_f32", [=] { potrf_checks(L, order, n, cx, cy, cv, zout, Lb, Inv, logdet, status, c); },
            L.stream);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n, const double* cx, const double* cy,
                             const double* cv, double* zout, double* Lb, double* Inv, double* logdet,
@@ -514,7 +535,7 @@ hipError_t launch_potrf_f64(const Launch& L, const int32_t* order, int n, const 
   if (cv && c.n_blocks > 0 && (!c.subsets || c.n_subsets <= 0)) return hipErrorInvalidValue;
   launched("potrf_f64", [=] { potrf_checks(L, order, n, cx, cy, cv, zout, Lb, Inv, logdet, status, c); },
            L.stream);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 template <typename T>
 static hipError_t trsv(const char* what, const Launch& L, const int32_t* order, int n, const T* Lb,
@@ -526,7 +547,7 @@ static hipError_t trsv(const char* what, const Launch& L, const int32_t* order, 
     dev_ptr(Lb, what); dev_ptr(Inv, what); dev_ptr(a, what); dev_ptr(b, what); dev_ptr(c, what); dev_ptr(d, what);
     dev_ptr(gate, what);
   }, L.stream);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_trsv_fwd_f32(const Launch& L, const int32_t* o, int n, int, const float* Lb, const double* Inv,
                                const double* rt, const double* rp, double* z, double* r2, const int32_t* g) {
@@ -555,7 +576,7 @@ hipError_t launch_residual(const Launch& L, const int2* ti, int nt, const int2* 
                           (const void*)pcol, (const void*)r, (const void*)gate})
       dev_ptr(p, "residual");
   }, L.stream);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_refine_gate(hipStream_t s, int n, const int32_t* order, int, int, const double* rhs2,
                               const double* ynorm2, double, int32_t* gate, int32_t* nsweep) {
@@ -565,7 +586,7 @@ hipError_t launch_refine_gate(hipStream_t s, int n, const int32_t* order, int, i
     for (const void* p : {(const void*)rhs2, (const void*)ynorm2, (const void*)gate, (const void*)nsweep})
       dev_ptr(p, "refine_gate");
   }, s);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_predict_val(const Launch& L, const int2* items, int n, const double* tx, const double* ty,
                               const double* vx, const double* vy, const double* yV, const double* alpha,
@@ -577,7 +598,7 @@ hipError_t launch_predict_val(const Launch& L, const int2* items, int n, const d
                           (const void*)alpha, (const void*)yhat, (const void*)err})
       dev_ptr(p, "predict_val");
   }, L.stream);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* theta, const KrigeItem* items,
                         int n, const double* tx, const double* ty, const double* L64, const double* Inv,
@@ -592,7 +613,7 @@ hipError_t launch_krige(hipStream_t s, const SubsetDesc* desc, const ThetaDev* t
                           (const void*)mean, (const void*)var})
       dev_ptr(p, "krige");
   }, s);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_gls(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n, int, int64_t,
                       const double* Xp, const double* Wp, const double* alpha, double* beta, int32_t* status) {
@@ -603,7 +624,7 @@ hipError_t launch_gls(hipStream_t s, const SubsetDesc* desc, const int32_t* orde
                           (const void*)beta, (const void*)status})
       dev_ptr(p, "gls");
   }, s);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* order, int n, const double* yT,
                        const double* alpha, double* quad) {
@@ -612,7 +633,7 @@ hipError_t launch_quad(hipStream_t s, const SubsetDesc* desc, const int32_t* ord
     dev_range(order, 4 * (size_t)n, "quad order");
     dev_ptr(desc, "quad"); dev_ptr(yT, "quad"); dev_ptr(alpha, "quad"); dev_ptr(quad, "quad");
   }, s);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_theta, const double* err,
                          int32_t* status, const int32_t* active, const double* rhs2, const double* ynorm2, double,
@@ -626,7 +647,7 @@ hipError_t launch_reduce(hipStream_t s, const SubsetDesc* desc, int S, int n_the
     dev_range(nbad, 4 * (size_t)n_theta, "reduce nbad");
     dev_ptr(err, "reduce err"); dev_ptr(rhs2, "reduce rhs2"); dev_ptr(ynorm2, "reduce ynorm2");
   }, s);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 hipError_t launch_math_check(hipStream_t s, int64_t n, const double* t, const double* x, double* e, double* r) {
   if (n <= 0) return hipSuccess;
@@ -634,7 +655,7 @@ hipError_t launch_math_check(hipStream_t s, int64_t n, const double* t, const do
     dev_range(t, 8 * (size_t)n, "math t"); dev_range(x, 8 * (size_t)n, "math x");
     dev_range(e, 8 * (size_t)n, "math e"); dev_range(r, 8 * (size_t)n, "math r");
   }, s);
-  return hipSuccess;
+  return hipGetLastError();  // like the launch wrappers: a pending error surfaces here
 }
 
 // the device division and the fixed-array prediction need device code

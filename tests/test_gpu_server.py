@@ -239,3 +239,26 @@ def test_batching_window_with_evaluations(w_plain):
         np.testing.assert_array_equal(m, ma)
         np.testing.assert_array_equal(v, va)
     say(f"   batches {rep['n_batches']} for {len(reqs)} requests")
+
+
+def test_server_budget_errors_leave_the_problem_usable(w_plain):
+    """A workspace budget below one kriging item per slot is rejected
+    (PCV_ERR_INVALID), one that no device holds fails with PCV_ERR_OOM; the
+    problem serves normally afterwards, with the same bits as pcv_predict."""
+    th = pcv.theta(0.1, 0.05)
+    reqs = _requests(w_plain, 6, 13)
+    say("[case] server budget errors")
+    with pcv.Problem.from_workload(w_plain, prec="mixed") as P:
+        P.factor(th)
+        alone = _alone(P, reqs, [False] * len(reqs))
+        with pytest.raises(pcv.PcvError) as e:
+            pcv.Server(P, mem_budget=1024)
+        assert e.value.status == 1
+        with pytest.raises(pcv.PcvError) as e:
+            pcv.Server(P, mem_budget=1 << 50)
+        assert e.value.status == 2
+        with pcv.Server(P) as srv:
+            preds = [srv.wait(srv.submit_predict(q)) for q in reqs]
+    for (m, v), (ma, va) in zip(preds, alone):
+        np.testing.assert_array_equal(m, ma)
+        np.testing.assert_array_equal(v, va)

@@ -12,7 +12,9 @@ stand-in of the HIP runtime and of the kernel launchers
   oom       a memory cap below the problem's need: PCV_ERR_OOM with nothing
             left behind; a device allocation failing at each point of a
             multi-theta call: the workspace or plan that did not fit is
-            given up and the theta values go one at a time;
+            given up and the theta values go one at a time; the same at
+            each allocation of a server's creation (PCV_ERR_OOM, the problem
+            back on its own stream, nothing left behind);
   tune      the autotuner on three problems of two shapes in both
             precisions: timing, the cache file (written, then reused for the
             identical problem), evaluations, batches and a server after
@@ -83,6 +85,8 @@ def test_memory_cap_rejects_without_side_effects(driver):
     # completes; early failures give the workspace up, late ones keep it)
     m = re.search(r"oom_batch: (\d+) calls ok, (\d+) out of memory, (\d+) gave the workspace up", out)
     assert m and int(m.group(1)) == 60 and 0 < int(m.group(3)) < 60, out[-2000:]
+    m = re.search(r"oom_server: (\d+) created, (\d+) out of memory", out)
+    assert m and int(m.group(1)) > 0 and int(m.group(2)) > 0, out[-2000:]
 
 
 def test_tuner_cycle_clean_under_sanitizers(driver):
