@@ -103,8 +103,10 @@ struct DeviceReader {
     if (count == 0) return PCV_OK;
     hipError_t e = hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
       return fail(PCV_ERR_DEVICE, std::string("reading ") + what + ": " + hipGetErrorString(e));
+    }
     return PCV_OK;
   }
 };
@@ -157,7 +159,10 @@ pcv_status pcv_selftest_math(int64_t n, const double* t, const double* x, double
   if (err == hipSuccess) err = hipMemcpy(e, d + 2 * n, bytes, hipMemcpyDeviceToHost);
   if (err == hipSuccess) err = hipMemcpy(r, d + 3 * n, bytes, hipMemcpyDeviceToHost);
   (void)hipFree(d);
-  if (err != hipSuccess) return fail(PCV_ERR_DEVICE, hipGetErrorString(err));
+  if (err != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PCV_ERR_DEVICE, hipGetErrorString(err));
+  }
   return PCV_OK;
 }
 

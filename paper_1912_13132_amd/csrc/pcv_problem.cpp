@@ -561,6 +561,7 @@ pcv_status ensure_post_streams(pcv_problem* p) {
       if (ep[q]) (void)hipEventDestroy(ep[q]);
       if (st[q]) (void)hipStreamDestroy(st[q]);
     }
+    (void)hipGetLastError();
     return fail(PCV_ERR_DEVICE, std::string("post streams: ") + hipGetErrorString(e));
   }
   for (int q = 0; q < 2; ++q) {
@@ -861,6 +862,7 @@ pcv_status capture_eval(pcv_problem* p, bool mixed, int sweeps, hipGraphExec_t* 
   if (e != hipSuccess) {
     for (hipStream_t x : {cs, cps[0], cps[1]})
       if (x) (void)hipStreamDestroy(x);
+    (void)hipGetLastError();
     return fail(PCV_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
   }
   hipGraph_t g = nullptr;
@@ -883,6 +885,7 @@ pcv_status capture_eval(pcv_problem* p, bool mixed, int sweeps, hipGraphExec_t* 
   for (hipStream_t x : {cps[1], cps[0]})
     if (x) (void)hipStreamDestroy(x);
   (void)hipStreamDestroy(cs);
+  if (s != PCV_OK) (void)hipGetLastError();  // reported here, not again at a later launch
   return s;
 }
 
@@ -1481,6 +1484,7 @@ pcv_status eval_batch_impl(pcv_problem* p, int32_t K, const pcv_theta* thetas, d
         if (s != PCV_OK) return s;
         if (e != hipSuccess) {
           pl->graph = nullptr;
+          (void)hipGetLastError();
           return fail(PCV_ERR_DEVICE, std::string("batch graph: ") + hipGetErrorString(e));
         }
       }

@@ -306,6 +306,7 @@ void completer(pcv_server* s) {
         // drop the request's queries that are still queued
         r->failed = true;
         r->err = std::string("kriging batch: ") + hipGetErrorString(e);
+        (void)hipGetLastError();
         if (r->next < r->q) {
           s->queued_q -= r->q - r->next;
           r->next = r->q = std::max(r->next, r->done);
@@ -400,7 +401,10 @@ void free_slots_mem(pcv_server* s) {
 pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, int32_t max_inflight,
                          int32_t n_slots) {
   hipError_t e = hipSetDevice(p->device);
-  if (e != hipSuccess) return fail(PCV_ERR_DEVICE, hipGetErrorString(e));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PCV_ERR_DEVICE, hipGetErrorString(e));
+  }
   // evaluations of a served problem stay on its one stream
   pcv_status st0 = set_served(p, true);
   if (st0 != PCV_OK) return st0;
@@ -427,6 +431,7 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
   if (e != hipSuccess) {
     delete s;
     (void)set_served(p, false);
+    (void)hipGetLastError();
     return fail(PCV_ERR_DEVICE, std::string("server stream: ") + hipGetErrorString(e));
   }
   s->slots.resize(n_slots);
