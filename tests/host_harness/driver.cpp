@@ -362,6 +362,36 @@ void tune_after_serving(const Data& d) {
   EXPECT(Live::now() == base);
 }
 
+// Tuning with a device or pinned allocation failing at each point in turn,
+// on a problem whose first evaluation happens inside the tuner and on one
+// evaluated and factored before: the tuner returns OK or the failure, the
+// problem keeps evaluating, and nothing is left behind.
+void oom_tune(const Data& d) {
+  const Live base = Live::now();
+  const pcv_theta t = th(0.4, 0.1);
+  int ok = 0, failed = 0;
+  for (int pre = 0; pre < 2; ++pre)
+    for (int64_t k = 0; k < 40; ++k) {
+      pcv_options o;
+      pcv_default_options(&o);
+      pcv_problem* p = create(d, o);
+      if (pre) {
+        evals(p, 1);
+        CHECK(pcv_factor(p, &t));
+      }
+      pcv_tune_report r;
+      stub_fail_malloc_after(k);
+      const pcv_status s = pcv_autotune(p, &t, nullptr, 1, &r);
+      stub_fail_malloc_after(-1);
+      EXPECT(s == PCV_OK || s == PCV_ERR_OOM);
+      if (s == PCV_OK) ++ok; else ++failed;
+      evals(p, 2);
+      CHECK(pcv_problem_destroy(p));
+    }
+  EXPECT(Live::now() == base);
+  std::printf("oom_tune: %d tuned, %d out of memory\n", ok, failed);
+}
+
 int main(int argc, char** argv) {
   const std::string sc = argc > 1 ? argv[1] : "sequence";
   const Data d = make_data(300, 1);
@@ -372,6 +402,7 @@ int main(int argc, char** argv) {
     oom(d);
     oom_batch(make_data(40, 3));
     oom_server(make_data(40, 4));
+    oom_tune(make_data(120, 6));
   } else if (sc == "tune_after_serving") {
     tune_after_serving(make_data(290, 2));
     stub_report("tune_after_serving");
