@@ -27,6 +27,7 @@ int64_t stub_live_streams();
 int64_t stub_live_events();
 void stub_report(const char* tag);
 void stub_fail_malloc_after(int64_t n);
+void stub_fail_launch_after(int64_t n);
 }
 
 #define CHECK(x)                                                                                   \
@@ -392,6 +393,89 @@ void oom_tune(const Data& d) {
   std::printf("oom_tune: %d tuned, %d out of memory\n", ok, failed);
 }
 
+// A kernel launch failing at each point in turn: of an evaluation (graph
+// capture and the fallback paths included), of a multi-theta call, of a
+// factorisation with a prediction, and of a server's kriging batches and
+// evaluations.  The call reports PCV_ERR_DEVICE (or OK when it launched
+// fewer kernels), nothing is left behind, and the next calls give the same
+// results as before the failure.
+void launch_fail(const Data& d) {
+  const Live base = Live::now();
+  const pcv_theta t = th(0.3, 0.1);
+  std::vector<pcv_theta> ths;
+  for (int k = 0; k < 5; ++k) ths.push_back(th(0.25 + 0.02 * k, 0.08));
+  std::vector<double> q = {0.3, 0.4, 0.7, 0.2, 0.1, 0.9};
+  int ok = 0, failed = 0;
+  for (int mode = 0; mode < 4; ++mode)
+    for (int64_t k = 0; k < 40; ++k) {
+      pcv_options o;
+      pcv_default_options(&o);
+      o.est_error = k & 1;
+      pcv_problem* p = create(d, o);
+      double ref = 0, l = 0;
+      std::vector<double> refb(ths.size()), lb(ths.size());
+      std::vector<double> m0(3), v0(3), m1(3), v1(3);
+      // every other round the failing call is the problem's first, so that
+      // the failure can hit the graph captures and the first allocations
+      const bool first = (k & 2) && mode < 2;
+      if (!first) {
+        CHECK(pcv_eval(p, &t, &ref, nullptr));
+        CHECK(pcv_eval_batch(p, (int32_t)ths.size(), ths.data(), refb.data()));
+        CHECK(pcv_factor(p, &t));
+        CHECK(pcv_predict(p, 3, q.data(), m0.data(), v0.data(), 0, nullptr));
+      }
+      pcv_status s = PCV_OK;
+      stub_fail_launch_after(k);
+      if (mode == 0) {
+        s = pcv_eval(p, &t, &l, nullptr);
+      } else if (mode == 1) {
+        s = pcv_eval_batch(p, (int32_t)ths.size(), ths.data(), lb.data());
+      } else if (mode == 2) {
+        s = pcv_factor(p, &t);
+        if (s == PCV_OK) s = pcv_predict(p, 3, q.data(), m1.data(), v1.data(), 0, nullptr);
+      } else {
+        pcv_server* srv = nullptr;
+        s = pcv_server_create(&srv, p, (size_t)64 << 20, 8);
+        if (s == PCV_OK) {
+          pcv_ticket a, b;
+          const pcv_status sa = pcv_server_submit_predict(srv, 3, q.data(), m1.data(), v1.data(), 0, &a);
+          const pcv_status sb = pcv_server_submit_eval(srv, &t, &l, &b);
+          pcv_status wa = sa == PCV_OK ? pcv_server_wait(srv, a, -1.0) : sa;
+          pcv_status wb = sb == PCV_OK ? pcv_server_wait(srv, b, -1.0) : sb;
+          EXPECT(wa == PCV_OK || wa == PCV_ERR_DEVICE);
+          EXPECT(wb == PCV_OK || wb == PCV_ERR_DEVICE);
+          s = wa != PCV_OK ? wa : wb;
+          stub_fail_launch_after(-1);
+          // the server keeps serving after a failed batch or evaluation
+          CHECK(pcv_server_submit_predict(srv, 3, q.data(), m1.data(), v1.data(), 0, &a));
+          CHECK(pcv_server_wait(srv, a, -1.0));
+          for (int i = 0; i < 3; ++i) EXPECT(m1[i] == m0[i] && v1[i] == v0[i]);
+          CHECK(pcv_server_destroy(srv));
+        }
+      }
+      stub_fail_launch_after(-1);
+      EXPECT(s == PCV_OK || s == PCV_ERR_DEVICE);
+      if (s == PCV_OK) ++ok; else ++failed;
+      if (first) {
+        CHECK(pcv_eval(p, &t, &ref, nullptr));
+        CHECK(pcv_eval_batch(p, (int32_t)ths.size(), ths.data(), refb.data()));
+        CHECK(pcv_factor(p, &t));
+        CHECK(pcv_predict(p, 3, q.data(), m0.data(), v0.data(), 0, nullptr));
+      }
+      // the problem is usable and gives the same results
+      CHECK(pcv_eval(p, &t, &l, nullptr));
+      EXPECT(l == ref);
+      CHECK(pcv_eval_batch(p, (int32_t)ths.size(), ths.data(), lb.data()));
+      for (size_t i = 0; i < ths.size(); ++i) EXPECT(lb[i] == refb[i]);
+      CHECK(pcv_factor(p, &t));
+      CHECK(pcv_predict(p, 3, q.data(), m1.data(), v1.data(), 0, nullptr));
+      for (int i = 0; i < 3; ++i) EXPECT(m1[i] == m0[i] && v1[i] == v0[i]);
+      CHECK(pcv_problem_destroy(p));
+    }
+  EXPECT(Live::now() == base);
+  std::printf("launch_fail: %d completed, %d failed\n", ok, failed);
+}
+
 int main(int argc, char** argv) {
   const std::string sc = argc > 1 ? argv[1] : "sequence";
   const Data d = make_data(300, 1);
@@ -403,6 +487,7 @@ int main(int argc, char** argv) {
     oom_batch(make_data(40, 3));
     oom_server(make_data(40, 4));
     oom_tune(make_data(120, 6));
+    launch_fail(make_data(60, 7));
   } else if (sc == "tune_after_serving") {
     tune_after_serving(make_data(290, 2));
     stub_report("tune_after_serving");

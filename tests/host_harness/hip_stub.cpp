@@ -69,6 +69,10 @@ int64_t g_fail_after = -1;
 // The runtime's per-thread last error: a failed call sets it, hipGetLastError
 // returns and clears it (the launch wrappers return it after each launch).
 thread_local hipError_t g_last_error = hipSuccess;
+// Launch failure injection: with g_fail_launch_after >= 0, that many more
+// kernel launches succeed and the next one fails (hipErrorLaunchFailure as
+// the launch's error; the kernel does not run).
+int64_t g_fail_launch_after = -1;
 constexpr size_t kStubMaxAlloc = (size_t)1 << 40;
 struct Alloc {
   size_t size;
@@ -159,6 +163,10 @@ extern "C" {
 void stub_fail_malloc_after(int64_t n) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   g_fail_after = n;
+}
+void stub_fail_launch_after(int64_t n) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  g_fail_launch_after = n;
 }
 
 int64_t stub_live_allocations() {
@@ -496,6 +504,11 @@ namespace pcv {
 static void launched(const char* what, std::function<void()> chk, hipStream_t s) {
   {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if (g_fail_launch_after == 0) {
+      g_last_error = hipErrorLaunchFailure;
+      return;
+    }
+    if (g_fail_launch_after > 0) --g_fail_launch_after;
     ++g_launches;
   }
   chk();  // arguments valid when the launch is enqueued

@@ -89,6 +89,8 @@ def test_memory_cap_rejects_without_side_effects(driver):
     assert m and int(m.group(1)) > 0 and int(m.group(2)) > 0, out[-2000:]
     m = re.search(r"oom_tune: (\d+) tuned, (\d+) out of memory", out)
     assert m and int(m.group(1)) > 0 and int(m.group(2)) > 0, out[-2000:]
+    m = re.search(r"launch_fail: (\d+) completed, (\d+) failed", out)
+    assert m and int(m.group(1)) > 0 and int(m.group(2)) > 0, out[-2000:]
 
 
 def test_tuner_cycle_clean_under_sanitizers(driver):
