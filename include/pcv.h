@@ -261,8 +261,8 @@ pcv_status pcv_eval_grid(pcv_problem* p, int32_t n_theta, const pcv_theta* theta
  *                      subset pads to at most this many rows use 4-wave
  *                      work-groups with 64-column panels, the others 8-wave
  *                      ones with 128-column panels (candidates 0, 1,024,
- *                      1,536 = the default, 2,048, 3,072, 4,096; FP64 always
- *                      uses 8-wave ones);
+ *                      1,408 = the default, 1,536, 2,048, 3,072, 4,096;
+ *                      FP64 always uses 8-wave ones);
  *   max_wg_per_subset  work-groups sharing one large subset in the first
  *                      launch (1, 2, 3, 4, 6, 8; see pcv_options);
  *   two_groups         1: the largest subsets in whole rounds of one

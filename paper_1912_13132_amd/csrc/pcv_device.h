@@ -93,10 +93,10 @@ struct CoopPlan {
 // max_npad: the largest padded size among the listed subsets.  FP32 launches
 // with max_npad <= small_npad use workgroups of 4 waves (64-column panels,
 // two per compute unit), the others 8 waves; FACTOR_SMALL_NPAD is the
-// measured crossover for uniform sizes (equal times at n = 1,500).  n_items
-// counts launch blocks (with cp, the cooperative blocks included; cp needs
-// the 8-wave shape).
-constexpr int FACTOR_SMALL_NPAD = 1536;
+// measured crossover for uniform sizes (4 waves faster up to n = 1,250,
+// equal at 1,400, slower from 1,500).  n_items counts launch blocks (with
+// cp, the cooperative blocks included; cp needs the 8-wave shape).
+constexpr int FACTOR_SMALL_NPAD = 1408;
 // ... and those whose largest subset has npad <= tiny_npad 2-wave
 // workgroups (64-column panels, 64-row chunks, four per compute unit);
 // measured on uniform sizes: faster up to n = 600, equal at 700, slower

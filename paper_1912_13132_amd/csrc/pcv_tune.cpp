@@ -176,7 +176,7 @@ pcv_status autotune_impl(pcv_problem* p, const pcv_theta& th, const char* cache_
     r.default_s = best_t;
     const bool mixed = p->opt.prec == PCV_PREC_MIXED;
     if (mixed)
-      for (int32_t sn : {0, 1024, 1536, 2048, 3072, 4096}) {
+      for (int32_t sn : {0, 1024, 1408, 1536, 2048, 3072, 4096}) {
         Cfg c = best;
         c.small_npad = sn;
         double t = 0.0;

@@ -54,7 +54,7 @@ def test_tune_three_problems_cache_and_parity(datas, refs, prec, tmp_path):
             rep = P.autotune(th, cache=cache, reps=2)
             say(f"   {rep}")
             assert rep["from_cache"] == expect_cache
-            assert rep["small_npad"] in (0, 1024, 1536, 2048, 3072, 4096)
+            assert rep["small_npad"] in (0, 1024, 1408, 1536, 2048, 3072, 4096)
             assert 1 <= rep["max_wg_per_subset"] <= 8 and rep["two_groups"] in (0, 1)
             if not expect_cache:
                 assert rep["n_timed"] >= 2 and 0 < rep["best_s"] <= rep["default_s"]
