@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <string>
@@ -72,15 +73,29 @@ struct Piece {
   int64_t r0, cnt, b0;  // queries [r0, r0+cnt) of r are batch queries [b0, b0+cnt)
 };
 
+// A batch's inputs travel in one copy and its results in another: the
+// query coordinates, original positions, flags and items are packed back to
+// back in one buffer (in_layout), the means and variances in another.
+struct InLayout {
+  size_t qy, qorig, qflag, items, bytes;
+};
+InLayout in_layout(int64_t nq, int64_t ni) {
+  InLayout L;
+  L.qy = 8 * (size_t)nq;
+  L.qorig = 16 * (size_t)nq;
+  L.qflag = 20 * (size_t)nq;
+  L.items = (24 * (size_t)nq + 15) & ~(size_t)15;
+  L.bytes = L.items + sizeof(KrigeItem) * (size_t)ni;
+  return L;
+}
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  double *d_qx = nullptr, *d_qy = nullptr, *d_mean = nullptr, *d_var = nullptr, *d_W = nullptr;
-  int32_t *d_qorig = nullptr, *d_qflag = nullptr;
-  KrigeItem* d_items = nullptr;
-  double *h_qx = nullptr, *h_qy = nullptr, *h_mean = nullptr, *h_var = nullptr;
-  int32_t *h_qorig = nullptr, *h_qflag = nullptr;
-  KrigeItem* h_items = nullptr;
+  char *d_in = nullptr, *h_in = nullptr;      // packed batch inputs (in_layout)
+  double *d_out = nullptr, *h_out = nullptr;  // means [0, nq), variances [nq, 2 nq)
+  double* d_W = nullptr;                      // variance scratch
+  const double *h_mean = nullptr, *h_var = nullptr;  // the last batch's results in h_out
   std::vector<Piece> pieces;
   int64_t nq = 0;
   bool any_var = false;
@@ -239,26 +254,25 @@ void batcher(pcv_server* s) {
     }
     plan_krige(p, nq, ql.data(), owner.data(), flags.data(), 0, plan);
     const size_t ni = plan.items.size();
-    std::copy(plan.qx.begin(), plan.qx.end(), sl.h_qx);
-    std::copy(plan.qy.begin(), plan.qy.end(), sl.h_qy);
-    std::copy(plan.qorig.begin(), plan.qorig.end(), sl.h_qorig);
-    std::copy(plan.qflag.begin(), plan.qflag.end(), sl.h_qflag);
-    std::copy(plan.items.begin(), plan.items.end(), sl.h_items);
+    const InLayout L = in_layout(nq, (int64_t)ni);
+    std::memcpy(sl.h_in, plan.qx.data(), 8 * (size_t)nq);
+    std::memcpy(sl.h_in + L.qy, plan.qy.data(), 8 * (size_t)nq);
+    std::memcpy(sl.h_in + L.qorig, plan.qorig.data(), 4 * (size_t)nq);
+    std::memcpy(sl.h_in + L.qflag, plan.qflag.data(), 4 * (size_t)nq);
+    std::memcpy(sl.h_in + L.items, plan.items.data(), sizeof(KrigeItem) * ni);
+    sl.h_mean = sl.h_out;
+    sl.h_var = sl.h_out + nq;
     hipError_t e = hipSuccess;
     hipStream_t st = sl.stream;
-    if (e == hipSuccess) e = hipMemcpyAsync(sl.d_qx, sl.h_qx, 8 * nq, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(sl.d_qy, sl.h_qy, 8 * nq, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(sl.d_qorig, sl.h_qorig, 4 * nq, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(sl.d_qflag, sl.h_qflag, 4 * nq, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sl.d_in, sl.h_in, L.bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(KrigeItem) * ni, hipMemcpyHostToDevice, st);
+      e = launch_krige(st, p->d_desc_fact, p->d_theta_fact, reinterpret_cast<const KrigeItem*>(sl.d_in + L.items),
+                       (int)ni, p->d_tx, p->d_ty, p->d_Lf, p->d_Invf, p->d_alpha_fact,
+                       reinterpret_cast<const double*>(sl.d_in), reinterpret_cast<const double*>(sl.d_in + L.qy),
+                       reinterpret_cast<const int32_t*>(sl.d_in + L.qorig),
+                       reinterpret_cast<const int32_t*>(sl.d_in + L.qflag), sl.d_W, sl.d_out, sl.d_out + nq);
     if (e == hipSuccess)
-      e = launch_krige(st, p->d_desc_fact, p->d_theta_fact, sl.d_items, (int)ni, p->d_tx, p->d_ty, p->d_Lf,
-                       p->d_Invf, p->d_alpha_fact, sl.d_qx, sl.d_qy, sl.d_qorig, sl.d_qflag, sl.d_W,
-                       sl.d_mean, sl.d_var);
-    if (e == hipSuccess) e = hipMemcpyAsync(sl.h_mean, sl.d_mean, 8 * nq, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && sl.any_var)
-      e = hipMemcpyAsync(sl.h_var, sl.d_var, 8 * nq, hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(sl.h_out, sl.d_out, (sl.any_var ? 16 : 8) * (size_t)nq, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(sl.done, st);
     sl.err = e;
     {
@@ -378,11 +392,9 @@ double pct(std::vector<double> v, double f) {
 
 void free_slots_mem(pcv_server* s) {
   for (Slot& sl : s->slots) {
-    for (void* d : {(void*)sl.d_qx, (void*)sl.d_qy, (void*)sl.d_mean, (void*)sl.d_var, (void*)sl.d_W,
-                    (void*)sl.d_qorig, (void*)sl.d_qflag, (void*)sl.d_items})
+    for (void* d : {(void*)sl.d_in, (void*)sl.d_out, (void*)sl.d_W})
       if (d) (void)hipFree(d);
-    for (void* h : {(void*)sl.h_qx, (void*)sl.h_qy, (void*)sl.h_mean, (void*)sl.h_var, (void*)sl.h_qorig,
-                    (void*)sl.h_qflag, (void*)sl.h_items})
+    for (void* h : {(void*)sl.h_in, (void*)sl.h_out})
       if (h) (void)hipHostFree(h);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -439,21 +451,12 @@ pcv_status server_create(pcv_server** out, pcv_problem* p, size_t mem_budget, in
     const int64_t Q = s->q_cap, I = s->item_cap;
     e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_qx, 8 * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_qy, 8 * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_mean, 8 * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_var, 8 * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_qorig, 4 * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_qflag, 4 * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_items, sizeof(KrigeItem) * I);
+    const size_t in_cap = in_layout(Q, I).bytes;
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_in, in_cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_out, 16 * Q);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_W, 8 * s->w_cap);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_qx, 8 * Q, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_qy, 8 * Q, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_mean, 8 * Q, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_var, 8 * Q, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_qorig, 4 * Q, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_qflag, 4 * Q, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_items, sizeof(KrigeItem) * I, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_in, in_cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_out, 16 * Q, hipHostMallocDefault);
     if (e != hipSuccess) break;
     s->ws_bytes += (size_t)Q * 40 + sizeof(KrigeItem) * I + 8 * (size_t)s->w_cap;
   }
